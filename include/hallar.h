@@ -1,0 +1,221 @@
+/*
+ * hallar.h -- C ABI of the MI355X (gfx950) HALLaR hot path.
+ *
+ * The library solves the primal-dual SDP pair (P)/(D) of the cuHALLaR paper
+ * (arXiv 2505.13719, Section 1):
+ *
+ *     min  C . X   s.t.  A_l . X = b_l (l = 1..m),  Tr X <= tau^2,  X PSD
+ *
+ * with the factorisation X = U U^T.  Each data matrix A_l (A_0 = C) is given
+ * in the hybrid sparse / low-rank form of Section 3.2 (eq. HSLR-rep-body):
+ * a sparse symmetric part listed by its upper-triangle entries plus, for the
+ * objective only, a low-rank term K D K^T.
+ *
+ * Conventions shared by every call
+ *   - Every call returns hallar_status; nothing throws or aborts across the
+ *     ABI.  On failure hallar_last_error(h) (or hallar_last_error(NULL) for
+ *     calls without a handle) returns a message owned by the library, valid
+ *     until the next failing call on the same thread.
+ *   - "device" pointers are HIP device allocations owned by the caller (for
+ *     example torch tensors on cuda:0); "host" pointers are ordinary memory.
+ *     The library never frees caller memory.  It copies what it keeps.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Operator calls are asynchronous on that stream unless a host scalar
+ *     is returned.  A handle is not thread-safe; use one per thread.
+ *   - Dense row-major layouts: element (i, c) of an n x r matrix with
+ *     leading dimension ld is at [i * ld + c].
+ *   - All allocation happens in hallar_create / hallar_pool_*; the operator
+ *     and solve calls allocate nothing.
+ */
+#ifndef HALLAR_H
+#define HALLAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hallar_s *hallar_t;
+typedef struct hallar_pool_s *hallar_pool_t;
+
+typedef enum {
+  HALLAR_OK = 0,
+  HALLAR_E_INVALID = 1,        /* bad argument, shape or index (i > j, l > m, ...) */
+  HALLAR_E_UNSUPPORTED = 2,    /* valid input outside what this build implements */
+  HALLAR_E_OOM = 3,            /* device memory / pool budget exhausted */
+  HALLAR_E_HIP = 4,            /* a HIP runtime call failed */
+  HALLAR_E_NOT_CONVERGED = 5,  /* eigen solve stopped above its tolerance */
+  HALLAR_E_ITER_LIMIT = 6,     /* an iteration cap of the solver was reached */
+  HALLAR_E_TIME_LIMIT = 7,     /* the solve's wall-clock limit was reached */
+  HALLAR_E_RANK_CAP = 8,       /* reserved: rank cap could not be honoured */
+  HALLAR_E_NUMERICAL = 9,      /* NaN/Inf, or the prox stepsize underflowed */
+  HALLAR_E_BUSY = 10           /* pool: no free slot right now */
+} hallar_status;
+
+/* Arithmetic of the operator hot path.  FP64: everything in double.
+ * FP32_MIXED: U, the sparse values and the SDDMM/SpMM/vector work in float;
+ * every reduction, the multipliers, the Lanczos basis, Ritz values, the dual
+ * objective, gap and infeasibility norms in double. */
+typedef enum { HALLAR_FP64 = 0, HALLAR_FP32_MIXED = 1 } hallar_precision;
+
+/* Problem descriptor (host memory, read during hallar_create only).
+ * Sparse part: nnz entries (row[k], col[k], con[k], val[k]) with
+ * 0 <= row[k] <= col[k] < n and 0 <= con[k] <= m, meaning
+ * (A_con)_{row,col} = (A_con)_{col,row} = val (con = 0 is C).  Repeated
+ * (row, col, con) triples are summed.  Low-rank part: n_lowrank terms; term t
+ * adds K_t D_t K_t^T to A_{lr_con[t]}, K_t is n x lr_rank[t] row-major at
+ * K + K_off[t], D_t is lr_rank[t] x lr_rank[t] row-major at D + D_off[t].
+ * This build supports low-rank terms on the objective only (lr_con = 0,
+ * at most one term, rank <= 2); others give HALLAR_E_UNSUPPORTED. */
+typedef struct {
+  int64_t n;             /* X is n x n, 1 <= n < 2^31 */
+  int64_t m;             /* number of constraints A_1..A_m, 0 <= m < 2^31 */
+  double trace_bound;    /* tau^2 > 0: Tr X <= tau^2, ||U||_F <= tau */
+  int64_t nnz;
+  const int32_t *row, *col, *con;
+  const double *val;
+  int32_t n_lowrank;
+  const int32_t *lr_con, *lr_rank;
+  const int64_t *K_off, *D_off;
+  const double *K, *D;
+  const double *b;       /* length m */
+} hallar_problem;
+
+/* Solver constants.  hallar_default_options() fills the values the library
+ * documents as its readings of the paper where the paper leaves them open. */
+typedef struct {
+  double eps;            /* relative tolerance of eq. termination2 (default 1e-5) */
+  double beta1, beta_growth, beta_max, infeas_ratio, pinf_gate;
+  double eps1, eps_floor, eps_decay;
+  double sigma, chi, lam0;          /* ADAP-AIPP / ADAP-FISTA universal parameters */
+  int32_t fista_max_iter, aipp_max_iter, hlr_max_iter, outer_max_iter;
+  double eig_tol, eig_frac;         /* Lanczos: residual <= max(eig_frac eps_t / tau^2, eig_tol max(1,|lambda|)) */
+  int32_t eig_kmax;                 /* Lanczos basis size before a thick restart (<= 128) */
+  int32_t eig_max_iter;             /* Lanczos matvec cap per eigen solve */
+  int32_t rank_cap;                 /* 0 = none (then at most 64 columns) */
+  double drop_tol;                  /* drop directions with sigma^2 <= drop_tol sigma_max^2 */
+  double time_limit;                /* seconds per solve */
+  uint64_t seed;                    /* Lanczos start vectors and default U0 */
+  int32_t verbose;
+} hallar_options;
+
+void hallar_default_options(hallar_options *opts);
+
+/* Result of a solve (all host scalars). */
+typedef struct {
+  int32_t status;        /* hallar_status of the solve: HALLAR_OK = converged */
+  int32_t rank;          /* columns of the final U */
+  int32_t outer_iters;
+  int32_t pad_;
+  double pval, dval;     /* C . U U^T and -b^T p - tau^2 theta */
+  double theta;          /* max(-lambda_min(C + A*(p)), 0) */
+  double pinf, gap, dinf;/* relative errors of eq. termination2 */
+  double beta;           /* final penalty */
+  double seconds;        /* wall-clock of the solve */
+  int64_t n_sddmm, n_spmm, n_matvec, n_fista_trials, n_aipp_iters;
+  int64_t n_hlr_iters, n_eig_calls, n_truncations, n_rounds;
+} hallar_result;
+
+typedef struct {
+  int32_t iters;         /* matrix-vector products */
+  int32_t restarts;
+  double residual;       /* ||G v - lambda v|| of the returned pair */
+} hallar_eig_info;
+
+/* Build a handle: dedups and sorts the entries, builds the union support S
+ * (Section 4.1, eq. def: support S ell), the index lists L_ij (eq. index
+ * list), the symmetric pattern S u S^T used by the adjoint (Alg. 4) and the
+ * tile schedule, and copies everything to device memory (Section 3.1: the
+ * problem data live on the device).  opts may be NULL (defaults).
+ * Errors: E_INVALID (bad shape/index), E_UNSUPPORTED, E_OOM, E_HIP. */
+hallar_status hallar_create(const hallar_problem *prob, hallar_precision prec,
+                            const hallar_options *opts, void *stream, hallar_t *out);
+hallar_status hallar_destroy(hallar_t h);
+const char *hallar_last_error(hallar_t h);
+
+/* Sizes of the handle's structures: pairs |S|, symmetric nnz of S u S^T,
+ * device bytes held. */
+hallar_status hallar_describe(hallar_t h, int64_t *pairs, int64_t *sym_nnz, int64_t *device_bytes);
+
+/* T = A~(U U^T) (Section 4, eq. A tilde operator; Algorithms 2 and 3):
+ * T[0] = C . UU^T, T[l] = A_l . UU^T for l = 1..m.
+ * U: device, n x r row-major with leading dimension ldu >= r, of the
+ * handle's operator type (double for FP64, float for FP32_MIXED);
+ * 1 <= r <= 64.  T: device double[m + 1].  Asynchronous on `stream`. */
+hallar_status hallar_eval_AUUt(hallar_t h, const void *U, int32_t r, int64_t ldu, double *T, void *stream);
+
+/* W = A~*(1, p) U = (C + sum_l p_l A_l) U (Section 4.2, eq. Adjoint
+ * calculation; Algorithms 4 and 5).  p: device double[m].  U as above; W:
+ * device n x r, leading dimension ldw >= r, operator type.  Asynchronous. */
+hallar_status hallar_adjoint_spmm(hallar_t h, const double *p, const void *U, int32_t r, int64_t ldu,
+                                  void *W, int64_t ldw, void *stream);
+
+/* Minimum eigenpair of G = C + A*(p) by thick-restart Lanczos in FP64 with
+ * full reorthogonalisation (the eigen step of Alg. 1, which the paper does not
+ * specify).  p: device double[m].  v0: device double[n] start vector or NULL
+ * (a seeded Gaussian).  Stops when ||G v - lambda v|| <= tol * max(1,|lambda|)
+ * or after max_iter products.  lambda: host; v: device double[n], unit
+ * norm.  Synchronises `stream`.  E_NOT_CONVERGED if the cap was reached
+ * (lambda and v then hold the best Ritz pair). */
+hallar_status hallar_min_eig(hallar_t h, const double *p, const double *v0, double tol, int32_t max_iter,
+                             double *lambda, double *v, hallar_eig_info *info, void *stream);
+
+/* Full HALLaR solve (Alg. 1 with ADAP-AIPP / ADAP-FISTA, Appendix A).
+ * U0: device double n x r0 (row-major, ld = r0) or NULL (n x 1 standard
+ * Gaussian from opts.seed, Section 5.1); it is projected onto ||U||_F <= tau.
+ * p0: device double[m] or NULL (zeros).  Blocks until done; res: host.
+ * res->status is the solve's outcome; the call itself returns HALLAR_OK
+ * unless the inputs were invalid or the device failed. */
+hallar_status hallar_solve(hallar_t h, const double *U0, int32_t r0, const double *p0, hallar_result *res);
+
+/* Copy the last solve's U (device double n x rank, leading dimension
+ * ldu >= rank) and p (device double[m]); either may be NULL. */
+hallar_status hallar_get_solution(hallar_t h, double *U, int64_t ldu, double *p, void *stream);
+
+/* Batched solve: `count` handles of the same precision solved together;
+ * their operator work runs in shared, segment-indexed kernel launches (one
+ * launch covers the tiles of every instance that needs that kernel).  U0s
+ * may be NULL or hold per-instance device pointers (n_k x 1) or NULLs. */
+hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *const *U0s,
+                                 hallar_result *results);
+
+/* ---- serving pool: continuous batching with HBM-footprint admission ---- */
+
+/* Device bytes an instance would hold in a pool (problem data + solver
+ * workspaces).  Deterministic: the pool admits by exactly this number. */
+hallar_status hallar_footprint(const hallar_problem *prob, hallar_precision prec,
+                               const hallar_options *opts, size_t *bytes);
+
+/* A pool owns up to hbm_budget bytes of device memory and at most
+ * max_active resident instances; all of them advance together, one batched
+ * round per step. */
+hallar_status hallar_pool_create(size_t hbm_budget, int32_t max_active, hallar_precision prec,
+                                 const hallar_options *opts, void *stream, hallar_pool_t *out);
+hallar_status hallar_pool_destroy(hallar_pool_t pool);
+
+/* Try to admit one request now.  Copies the problem to the device and
+ * starts its solve at the next step.  U0: host double n x 1 or NULL.
+ * Returns E_OOM if its footprint does not fit in the free budget and E_BUSY
+ * if max_active instances are resident; the caller retries later. */
+hallar_status hallar_pool_admit(hallar_pool_t pool, const hallar_problem *prob, const double *U0,
+                                int64_t ticket);
+
+/* Advance every resident instance by up to `rounds` batched rounds (each
+ * round: one host-device exchange of per-instance scalars).  Finished
+ * instances release their memory at the end of the round that finishes
+ * them.  n_active: host, resident instances after the step. */
+hallar_status hallar_pool_step(hallar_pool_t pool, int32_t rounds, int32_t *n_active);
+
+/* Collect up to cap finished solves (tickets and results, host arrays). */
+hallar_status hallar_pool_poll(hallar_pool_t pool, int64_t *tickets, hallar_result *results, int32_t cap,
+                               int32_t *n_done);
+
+/* Bytes in use / budget of the pool. */
+hallar_status hallar_pool_usage(hallar_pool_t pool, size_t *used, size_t *budget);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HALLAR_H */

@@ -1,0 +1,1317 @@
+// Round executor, device-memory layout of an instance, and the HALLaR solver
+// written as one C++20 coroutine per instance.
+//
+// A solve suspends at every device operation it needs (a FISTA trial, a
+// Lanczos block, a Frank-Wolfe update, ...).  A round collects the pending
+// operations of all resident instances, groups equal operations, launches
+// each group's kernels once over the concatenated tiles of its instances,
+// exchanges the per-instance scalars with the host in one copy each way and
+// resumes every coroutine.  A single solve is a pool with one instance.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+#include "ops.h"
+
+namespace hl {
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+#define HL_TRY(expr, msg)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      err = std::string(msg) + ": " + hipGetErrorString(e_);                           \
+      return HALLAR_E_HIP;                                                             \
+    }                                                                                  \
+  } while (0)
+
+// ------------------------------------------------------------------ arena
+bool Arena::init(size_t bytes, std::string &err) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (hipMalloc((void **)&base_, bytes) != hipSuccess) {
+    err = "hipMalloc of the pool slab failed";
+    base_ = nullptr;
+    return false;
+  }
+  cap_ = bytes;
+  used_ = 0;
+  free_.clear();
+  free_[0] = bytes;
+  return true;
+}
+void Arena::release() {
+  if (base_) (void)hipFree(base_);
+  base_ = nullptr;
+  cap_ = used_ = 0;
+  free_.clear();
+}
+size_t Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      const size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > bytes) free_[off + bytes] = sz - bytes;
+      used_ += bytes;
+      return off;
+    }
+  }
+  return SIZE_MAX;
+}
+void Arena::free(size_t off, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  used_ -= bytes;
+  auto it = free_.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    free_.erase(nx);
+  }
+  if (it != free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ layout
+int rcap_for(const hallar_options &o, int prec) {
+  const int cap = o.rank_cap > 0 ? std::min(o.rank_cap + 1, R_MAX) : R_MAX;
+  return r_bucket(cap, prec);
+}
+int kmax_for(const hallar_options &o, int n) {
+  int k = o.eig_kmax > 0 ? std::min(o.eig_kmax, KMAX) : KMAX;
+  return std::max(2, std::min(k, n));
+}
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct Layout {
+  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, b, K0, K064, D0;
+  size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
+  size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, gram, tiles, ilist;
+  size_t total;
+};
+
+static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
+  Layout L{};
+  Carve c;
+  const size_t sz = prec == 0 ? 8 : 4;
+  const size_t n = hp.n, m = hp.m, P = hp.npairs, nl = hp.nlower, E = hp.nentries;
+  L.rowptr_u = c.take((n + 1) * 4);
+  L.col_u = c.take(P * 4);
+  L.pcon = c.take(P * 4);
+  L.c_u = c.take(P * sz);
+  L.pa = c.take(P * sz);
+  L.c64 = c.take(P * 8);
+  L.pa64 = c.take(P * 8);
+  L.rowptr_l = c.take((n + 1) * 4);
+  L.col_l = c.take(nl * 4);
+  L.pid_l = c.take(nl * 4);
+  L.b = c.take(m * 8);
+  L.K0 = c.take(n * hp.r0 * sz);
+  L.K064 = c.take(n * hp.r0 * 8);
+  L.D0 = c.take(hp.r0 * hp.r0 * 8);
+  if (!hp.direct) {
+    L.eptr = c.take((P + 1) * 4);
+    L.econ = c.take(E * 4);
+    L.ea64 = c.take(E * 8);
+    L.ew64 = c.take(E * 8);
+    L.cptr = c.take((m + 1) * 4);
+    L.cent = c.take(E * 4);
+    L.epair = c.take(E * 4);
+    L.Bpair = c.take(P * 8);
+  }
+  for (int q = 0; q < NBUF; ++q) L.buf[q] = c.take(n * Rcap * sz);
+  L.m_xt = c.take(P * sz);
+  L.m_yp = c.take(P * sz);
+  L.p = c.take(m * 8);
+  L.yp = c.take(m * 8);
+  L.TY = c.take(m * 8);
+  L.Ty = c.take(m * 8);
+  L.m64 = c.take(P * 8);
+  L.V = c.take((size_t)(kmax + 1) * n * 8);
+  L.V2 = c.take((size_t)(kmax + 1) * n * 8);
+  L.w = c.take(n * 8);
+  L.lzv = c.take(n * 8);
+  L.hcoef = c.take((KMAX + 1) * 8);
+  L.Z0 = c.take(2 * LR_MAX * R_MAX * 8);
+  const size_t nt = hp.tiles.size();
+  L.part = c.take((nt + (m + BLOCK - 1) / BLOCK + 1) * PSTRIDE * 8);
+  L.gram = c.take(nt * (size_t)Rcap * Rcap * 8);
+  L.tiles = c.take(nt * sizeof(Tile));
+  L.ilist = c.take(sizeof(int32_t));
+  L.total = c.off;
+  return L;
+}
+
+size_t instance_bytes(const HostProblem &hp, int prec, int Rcap, int kmax) {
+  return make_layout(hp, prec, Rcap, kmax).total;
+}
+
+// ------------------------------------------------------------------ pool
+hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &opts, hipStream_t stream,
+                        size_t arena_bytes, int64_t tiles_cap, std::string &err) {
+  P.prec = prec;
+  P.opts = opts;
+  P.stream = stream;
+  P.max_slots = max_slots;
+  P.slots.resize(max_slots);
+  P.h_insts.assign(max_slots, InstDev{});
+  HL_TRY(hipMalloc((void **)&P.d_insts, sizeof(InstDev) * max_slots), "hipMalloc insts");
+  HL_TRY(hipMalloc((void **)&P.d_prm, sizeof(InstParams) * max_slots), "hipMalloc params");
+  HL_TRY(hipMalloc((void **)&P.d_res, sizeof(InstRes) * max_slots), "hipMalloc results");
+  HL_TRY(hipHostMalloc((void **)&P.h_prm, sizeof(InstParams) * max_slots, hipHostMallocDefault), "hipHostMalloc params");
+  HL_TRY(hipHostMalloc((void **)&P.h_res, sizeof(InstRes) * max_slots, hipHostMallocDefault), "hipHostMalloc results");
+  std::memset(P.h_prm, 0, sizeof(InstParams) * max_slots);
+  std::memset(P.h_res, 0, sizeof(InstRes) * max_slots);
+  HL_TRY(hipMemset(P.d_res, 0, sizeof(InstRes) * max_slots), "hipMemset results");
+  P.tiles_cap = std::max<int64_t>(tiles_cap, 4096);
+  HL_TRY(hipMalloc((void **)&P.d_tiles, sizeof(Tile) * P.tiles_cap), "hipMalloc tiles");
+  HL_TRY(hipHostMalloc((void **)&P.h_tiles, sizeof(Tile) * P.tiles_cap, hipHostMallocDefault), "hipHostMalloc tiles");
+  P.ilist_cap = 3 * (int64_t)max_slots + 16;
+  HL_TRY(hipMalloc((void **)&P.d_ilist, sizeof(int32_t) * P.ilist_cap), "hipMalloc ilist");
+  HL_TRY(hipHostMalloc((void **)&P.h_ilist, sizeof(int32_t) * P.ilist_cap, hipHostMallocDefault), "hipHostMalloc ilist");
+  P.up_cap = std::max<int64_t>(1 << 16, (int64_t)std::min(max_slots, 256) * KMAX * KMAX);
+  P.dl_cap = P.up_cap;
+  HL_TRY(hipMalloc((void **)&P.d_up, sizeof(double) * P.up_cap), "hipMalloc upload");
+  HL_TRY(hipHostMalloc((void **)&P.h_up, sizeof(double) * P.up_cap, hipHostMallocDefault), "hipHostMalloc upload");
+  HL_TRY(hipMalloc((void **)&P.d_dl, sizeof(double) * P.dl_cap), "hipMalloc download");
+  HL_TRY(hipHostMalloc((void **)&P.h_dl, sizeof(double) * P.dl_cap, hipHostMallocDefault), "hipHostMalloc download");
+  if (arena_bytes > 0) {
+    if (!P.arena.init(arena_bytes, err)) return HALLAR_E_OOM;
+    P.use_arena = true;
+    P.budget = arena_bytes;
+  }
+  return HALLAR_OK;
+}
+
+void pool_release(Pool &P) {
+  for (int s = 0; s < (int)P.slots.size(); ++s)
+    if (P.slots[s]) slot_unload(P, s);
+  auto fr = [](void *p) {
+    if (p) (void)hipFree(p);
+  };
+  auto frh = [](void *p) {
+    if (p) (void)hipHostFree(p);
+  };
+  fr(P.d_insts); fr(P.d_prm); fr(P.d_res); fr(P.d_tiles); fr(P.d_ilist); fr(P.d_up); fr(P.d_dl);
+  frh(P.h_prm); frh(P.h_res); frh(P.h_tiles); frh(P.h_ilist); frh(P.h_up); frh(P.h_dl);
+  P.d_insts = nullptr;
+  P.arena.release();
+}
+
+int pool_active(const Pool &P) {
+  int c = 0;
+  for (auto &s : P.slots)
+    if (s && s->used && !s->done && s->task) ++c;
+  return c;
+}
+
+template <typename T>
+static void put(char *base, size_t off, const std::vector<T> &v, hipStream_t st) {
+  if (!v.empty()) (void)hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
+  auto sl = std::make_unique<Slot>();
+  Slot &S = *sl;
+  S.hp = std::move(hp);
+  HostProblem &h = S.hp;
+  S.Rcap = rcap_for(P.opts, P.prec);
+  S.kmax = kmax_for(P.opts, h.n);
+  const Layout L = make_layout(h, P.prec, S.Rcap, S.kmax);
+  char *base = nullptr;
+  if (P.use_arena) {
+    const size_t off = P.arena.alloc(L.total);
+    if (off == SIZE_MAX) {
+      err = "pool budget exhausted";
+      return HALLAR_E_OOM;
+    }
+    S.slab_off = off;
+    base = P.arena.base() + off;
+  } else {
+    if (hipMalloc((void **)&base, L.total) != hipSuccess) {
+      err = "hipMalloc of the instance slab failed";
+      return HALLAR_E_OOM;
+    }
+  }
+  S.slab = base;
+  S.slab_bytes = L.total;
+  hipStream_t st = P.stream;
+  for (auto &t : h.tiles) t.inst = s;
+  // operator-type copies
+  const bool f32 = P.prec != 0;
+  auto conv = [&](const std::vector<double> &v, size_t off) {
+    if (v.empty()) return;
+    if (f32) {
+      std::vector<float> f(v.begin(), v.end());
+      (void)hipMemcpy(base + off, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    } else {
+      (void)hipMemcpy(base + off, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    }
+  };
+  put(base, L.rowptr_u, h.rowptr_u, st);
+  put(base, L.col_u, h.col_u, st);
+  put(base, L.pcon, h.pcon, st);
+  conv(h.c_u, L.c_u);
+  conv(h.pa, L.pa);
+  put(base, L.c64, h.c_u, st);
+  put(base, L.pa64, h.pa, st);
+  put(base, L.rowptr_l, h.rowptr_l, st);
+  put(base, L.col_l, h.col_l, st);
+  put(base, L.pid_l, h.pid_l, st);
+  put(base, L.b, h.b, st);
+  conv(h.K0, L.K0);
+  put(base, L.K064, h.K0, st);
+  put(base, L.D0, h.D0, st);
+  if (!h.direct) {
+    put(base, L.eptr, h.eptr, st);
+    put(base, L.econ, h.econ, st);
+    put(base, L.ea64, h.ea, st);
+    put(base, L.ew64, h.ew, st);
+    put(base, L.cptr, h.cptr, st);
+    put(base, L.cent, h.cent, st);
+    put(base, L.epair, h.epair, st);
+  }
+  put(base, L.tiles, h.tiles, st);
+  std::vector<int32_t> il{s};
+  put(base, L.ilist, il, st);
+  if (h.m > 0) (void)hipMemsetAsync(base + L.p, 0, (size_t)h.m * 8, st);
+  (void)hipMemsetAsync(base + L.Z0, 0, 2 * LR_MAX * R_MAX * 8, st);
+  for (int q = 0; q < NBUF; ++q) (void)hipMemsetAsync(base + L.buf[q], 0, (size_t)h.n * S.Rcap * (f32 ? 4 : 8), st);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    err = "upload of the instance failed";
+    return HALLAR_E_HIP;
+  }
+  InstDev &D = P.h_insts[s];
+  D = InstDev{};
+  D.n = h.n;
+  D.m = h.m;
+  D.npairs = (int32_t)h.npairs;
+  D.nlower = (int32_t)h.nlower;
+  D.r0 = h.r0;
+  D.direct = h.direct ? 1 : 0;
+  D.ntiles = (int32_t)h.tiles.size();
+  auto at = [&](size_t off) { return (void *)(base + off); };
+  D.rowptr_u = (const int32_t *)at(L.rowptr_u);
+  D.col_u = (const int32_t *)at(L.col_u);
+  D.pcon = (const int32_t *)at(L.pcon);
+  D.c_u = h.has_c ? at(L.c_u) : nullptr;
+  D.pa = at(L.pa);
+  D.c64 = h.has_c ? (const double *)at(L.c64) : nullptr;
+  D.pa64 = (const double *)at(L.pa64);
+  D.b = (const double *)at(L.b);
+  D.rowptr_l = (const int32_t *)at(L.rowptr_l);
+  D.col_l = (const int32_t *)at(L.col_l);
+  D.pid_l = (const int32_t *)at(L.pid_l);
+  D.K0 = at(L.K0);
+  D.K064 = (const double *)at(L.K064);
+  D.D0 = (const double *)at(L.D0);
+  if (!h.direct) {
+    D.eptr = (const int32_t *)at(L.eptr);
+    D.econ = (const int32_t *)at(L.econ);
+    D.ea64 = (const double *)at(L.ea64);
+    D.ew64 = (const double *)at(L.ew64);
+    D.cptr = (const int32_t *)at(L.cptr);
+    D.cent = (const int32_t *)at(L.cent);
+    D.epair = (const int32_t *)at(L.epair);
+    D.Bpair = (double *)at(L.Bpair);
+  }
+  for (int q = 0; q < NBUF; ++q) D.buf[q] = at(L.buf[q]);
+  D.m_xt = at(L.m_xt);
+  D.m_yp = at(L.m_yp);
+  D.p = (double *)at(L.p);
+  D.yp = (double *)at(L.yp);
+  D.TY = (double *)at(L.TY);
+  D.Ty = (double *)at(L.Ty);
+  D.m64 = (double *)at(L.m64);
+  D.V = (double *)at(L.V);
+  D.V2 = (double *)at(L.V2);
+  D.w = (double *)at(L.w);
+  D.lzv = (double *)at(L.lzv);
+  D.hcoef = (double *)at(L.hcoef);
+  D.Z0 = (double *)at(L.Z0);
+  D.up_base = P.d_up;
+  D.dl_base = P.d_dl;
+  D.part = (double *)at(L.part);
+  D.gram = (double *)at(L.gram);
+  D.prm = P.d_prm + s;
+  D.res = P.d_res + s;
+  S.dev = D;
+  S.used = true;
+  S.free_bufs.clear();
+  for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);
+  S.prm = InstParams{};
+  S.prm.tau2 = h.tau2;
+  S.prm.tau = std::sqrt(h.tau2);
+  S.cur_R = r_bucket(1, P.prec);
+  P.slots[s] = std::move(sl);
+  P.insts_dirty = true;
+  // tiles / ilist of the slot live in its slab
+  return HALLAR_OK;
+}
+
+void slot_unload(Pool &P, int s) {
+  if (!P.slots[s]) return;
+  Slot &S = *P.slots[s];
+  if (S.task) {
+    delete S.task;
+    S.task = nullptr;
+  }
+  if (S.slab) {
+    if (P.use_arena) P.arena.free(S.slab_off, S.slab_bytes);
+    else (void)hipFree(S.slab);
+  }
+  P.slots[s].reset();
+  P.h_insts[s] = InstDev{};
+  P.insts_dirty = true;
+}
+
+// ------------------------------------------------------------------ rounds
+int PendingOp::key() const {
+  return (int)code * 1000003 + R * 131 + R2 * 17 + xrole * 7 + (msel + 1) * 3 + wT * 5 + wyp * 11 + zsel * 13 +
+         src * 19 + dst * 23;
+}
+
+struct Group {
+  OpCode code;
+  int R, R2;
+  int64_t t0, nt;
+  int64_t i0, ni;
+  int64_t gi0, gni;  // general-mode instances
+  int64_t di0, dni;  // direct-mode instances
+  int maxm, maxp;
+  const PendingOp *op;
+  int first_slot;
+};
+
+static void launch_group(Pool &P, const Group &g) {
+  hipStream_t st = P.stream;
+  const Tile *T = P.d_tiles + g.t0;
+  const int nt = (int)g.nt;
+  const int32_t *IL = P.d_ilist + g.i0;
+  const int ni = (int)g.ni;
+  const int32_t *GL = P.d_ilist + g.gi0;
+  const int gni = (int)g.gni;
+  const int32_t *DL = P.d_ilist + g.di0;
+  const int dni = (int)g.dni;
+  const InstDev *D = P.d_insts;
+  const int prec = P.prec;
+  const int R = g.R;
+  const PendingOp &o = *g.op;
+  auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
+    op_lr_dots(prec, R, st, T, nt, D, xrole);
+    op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
+    if (gni > 0) {
+      op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
+      if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
+    }
+    op_reduce(st, IL, ni, D, red_op, zsel, R, 0);
+  };
+  switch (g.code) {
+    case OP_TRIAL:
+      op_combo(prec, R, st, T, nt, D);
+      op_reduce(st, IL, ni, D, RDH_COMBO, 0, R, 0);
+      sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
+      op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
+      op_reduce(st, IL, ni, D, RDH_TRIAL_PROJ, 0, R, 0);
+      op_proj(prec, R, st, T, nt, D);
+      op_reduce(st, IL, ni, D, RDH_PROJ_DOTS, 0, R, 0);
+      sddmm(RZ, 1, 0, 0, RDH_SDDMM_YP, 1);
+      break;
+    case OP_GRAD:
+      op_spmm(prec, R, st, T, nt, D, RZ, 1, 1, 0, SPM_AIPP);
+      op_reduce(st, IL, ni, D, RDH_AIPP, 0, R, 0);
+      break;
+    case OP_EVAL:
+      sddmm(o.xrole, o.msel, o.wT, o.wyp, RDH_EVAL, o.zsel);
+      break;
+    case OP_COPY:
+      op_copy_scale(prec, R, st, T, nt, D, o.src, o.dst);
+      op_reduce(st, IL, ni, D, RDH_NORM, 0, R, 0);
+      break;
+    case OP_PACK:
+      op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
+      op_reduce(st, IL, ni, D, RDH_NORM, 0, R, 0);
+      break;
+    case OP_LZ_BEGIN:
+      if (dni > 0) op_pairvals(prec, st, DL, dni, g.maxp, D, 2, nullptr, 0);
+      if (gni > 0) op_pairvals(prec, st, GL, gni, g.maxp, D, 2, nullptr, 1);
+      op_lz_start(st, T, nt, D);
+      op_reduce(st, IL, ni, D, RDH_LZ_START, 0, R, 0);
+      op_lz_first(st, T, nt, D);
+      break;
+    case OP_LZ_STEPS:
+      for (int k = 0; k < o.steps; ++k) {
+        op_lz_spmv(st, T, nt, D, 0);
+        op_lz_dots(st, T, nt, D);
+        op_reduce(st, IL, ni, D, RDH_LZ_H1, 0, R, 0);
+        op_lz_update(st, T, nt, D, 0);
+        op_lz_dots(st, T, nt, D);
+        op_reduce(st, IL, ni, D, RDH_LZ_H2, 0, R, 0);
+        op_lz_update(st, T, nt, D, 1);
+        op_reduce(st, IL, ni, D, RDH_LZ_FINAL, 0, R, 0);
+        op_lz_scale(st, T, nt, D);
+      }
+      break;
+    case OP_LZ_RITZ:
+      op_lz_combine(st, T, nt, D, 1);
+      break;
+    case OP_LZ_RESTART:
+      op_lz_combine(st, T, nt, D, 0);
+      break;
+    case OP_FW_PREP:
+      op_fw_den(st, T, nt, D);
+      if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
+      op_reduce(st, IL, ni, D, RDH_FW_DEN, 0, R, 0);
+      break;
+    case OP_FW_APPLY:
+      op_fw_apply(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      break;
+    case OP_SETP:
+      op_set_p(st, IL, ni, g.maxm, D);
+      op_reduce(st, IL, ni, D, RDH_SETP, 0, R, 0);
+      break;
+    case OP_GRAM:
+      op_gram(prec, R, st, T, nt, D, o.src);
+      op_reduce(st, IL, ni, D, RDH_GRAM, 0, R, 0);
+      break;
+    case OP_ROTATE:
+      op_rotate(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      break;
+    default:
+      break;
+  }
+}
+
+static hallar_status run_round(Pool &P, bool &did_work) {
+  did_work = false;
+  std::vector<int> ready;
+  for (int s = 0; s < (int)P.slots.size(); ++s) {
+    auto &sp = P.slots[s];
+    if (sp && sp->used && sp->has_op && !sp->done) ready.push_back(s);
+  }
+  if (ready.empty()) return HALLAR_OK;
+  std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) {
+    const PendingOp &x = P.slots[a]->op, &y = P.slots[b]->op;
+    const int kx = x.code == OP_PACK ? x.key() + a * 7919 : x.key();
+    const int ky = y.code == OP_PACK ? y.key() + b * 7919 : y.key();
+    return kx < ky;
+  });
+  int64_t up_used = 0, dl_used = 0, t_used = 0;
+  std::vector<int> run;
+  for (int s : ready) {
+    Slot &S = *P.slots[s];
+    const int64_t nup = (int64_t)S.op.upload.size(), ndl = S.op.dl_count, nt = (int64_t)S.hp.tiles.size();
+    if (up_used + nup > P.up_cap || dl_used + ndl > P.dl_cap || t_used + nt > P.tiles_cap) {
+      if (run.empty()) {
+        P.err = "an operation exceeds the staging capacity";
+        return HALLAR_E_UNSUPPORTED;
+      }
+      continue;
+    }
+    S.op.up_off = up_used;
+    if (nup) std::memcpy(P.h_up + up_used, S.op.upload.data(), nup * sizeof(double));
+    up_used += (nup + 7) & ~(int64_t)7;
+    S.op.dl_off = dl_used;
+    dl_used += (ndl + 7) & ~(int64_t)7;
+    t_used += nt;
+    run.push_back(s);
+  }
+  // groups
+  std::vector<Group> groups;
+  int64_t tpos = 0, ipos = 0;
+  size_t q = 0;
+  while (q < run.size()) {
+    size_t e = q;
+    const PendingOp &o = P.slots[run[q]]->op;
+    const int k0 = o.code == OP_PACK ? o.key() + run[q] * 7919 : o.key();
+    while (e < run.size()) {
+      const PendingOp &x = P.slots[run[e]]->op;
+      const int kx = x.code == OP_PACK ? x.key() + run[e] * 7919 : x.key();
+      if (kx != k0) break;
+      ++e;
+    }
+    Group g{};
+    g.code = o.code;
+    g.R = o.R;
+    g.R2 = o.R2;
+    g.op = &o;
+    g.t0 = tpos;
+    g.i0 = ipos;
+    for (size_t u = q; u < e; ++u) {
+      const int s = run[u];
+      Slot &S = *P.slots[s];
+      for (const Tile &t : S.hp.tiles) P.h_tiles[tpos++] = t;
+      P.h_ilist[ipos++] = s;
+      g.maxm = std::max(g.maxm, S.hp.m);
+      g.maxp = std::max<int>(g.maxp, (int)S.hp.npairs);
+    }
+    g.nt = tpos - g.t0;
+    g.ni = ipos - g.i0;
+    g.gi0 = ipos;
+    for (size_t u = q; u < e; ++u)
+      if (!P.slots[run[u]]->hp.direct) P.h_ilist[ipos++] = run[u];
+    g.gni = ipos - g.gi0;
+    g.di0 = ipos;
+    for (size_t u = q; u < e; ++u)
+      if (P.slots[run[u]]->hp.direct) P.h_ilist[ipos++] = run[u];
+    g.dni = ipos - g.di0;
+    groups.push_back(g);
+    q = e;
+  }
+  int maxs = 0;
+  for (int s : run) {
+    Slot &S = *P.slots[s];
+    for (int r = 0; r < NROLE; ++r)
+      if (S.prm.buf[r] < 0 || S.prm.buf[r] >= NBUF) {
+        P.err = "internal error: work buffers exhausted";
+        return HALLAR_E_UNSUPPORTED;
+      }
+    S.prm.up_off = S.op.up_off;
+    S.prm.dl_off = S.op.dl_off;
+    P.h_prm[s] = S.prm;
+    maxs = std::max(maxs, s + 1);
+  }
+  hipStream_t st = P.stream;
+  std::string &err = P.err;
+  if (P.insts_dirty) {
+    HL_TRY(hipMemcpyAsync(P.d_insts, P.h_insts.data(), sizeof(InstDev) * P.max_slots, hipMemcpyHostToDevice, st),
+           "upload descriptors");
+    P.insts_dirty = false;
+  }
+  HL_TRY(hipMemcpyAsync(P.d_prm, P.h_prm, sizeof(InstParams) * maxs, hipMemcpyHostToDevice, st), "upload params");
+  HL_TRY(hipMemcpyAsync(P.d_tiles, P.h_tiles, sizeof(Tile) * tpos, hipMemcpyHostToDevice, st), "upload tiles");
+  HL_TRY(hipMemcpyAsync(P.d_ilist, P.h_ilist, sizeof(int32_t) * ipos, hipMemcpyHostToDevice, st), "upload ilist");
+  if (up_used) HL_TRY(hipMemcpyAsync(P.d_up, P.h_up, sizeof(double) * up_used, hipMemcpyHostToDevice, st), "upload coef");
+  for (const Group &g : groups) launch_group(P, g);
+  HL_TRY(hipGetLastError(), "kernel launch");
+  HL_TRY(hipMemcpyAsync(P.h_res, P.d_res, sizeof(InstRes) * maxs, hipMemcpyDeviceToHost, st), "download results");
+  if (dl_used) HL_TRY(hipMemcpyAsync(P.h_dl, P.d_dl, sizeof(double) * dl_used, hipMemcpyDeviceToHost, st), "download");
+  HL_TRY(hipStreamSynchronize(st), "round");
+  P.rounds++;
+  did_work = true;
+  for (int s : run) {
+    Slot &S = *P.slots[s];
+    S.has_op = false;
+    S.result.n_rounds++;
+    if (S.op.dl_count) S.dl.assign(P.h_dl + S.op.dl_off, P.h_dl + S.op.dl_off + S.op.dl_count);
+    auto h = S.resume;
+    S.resume = {};
+    h.resume();
+  }
+  return HALLAR_OK;
+}
+
+// ------------------------------------------------------------------ solver
+struct OpAwait {
+  Slot &s;
+  bool await_ready() { return false; }
+  void await_suspend(std::coroutine_handle<> h) {
+    s.resume = h;
+    s.has_op = true;
+  }
+  void await_resume() {}
+};
+
+struct Ctx {
+  Pool &P;
+  Slot &S;
+  int idx;
+  const hallar_options &o;
+  double res(int k) const { return P.h_res[idx].v[k]; }
+  int alloc() {
+    if (S.free_bufs.empty()) return -1;
+    const int b = S.free_bufs.back();
+    S.free_bufs.pop_back();
+    return b;
+  }
+  void release(int b) {
+    if (b >= 0) S.free_bufs.push_back(b);
+  }
+  PendingOp &op(OpCode c) {
+    S.op = PendingOp{};
+    S.op.code = c;
+    // FP64 vector ops (Lanczos, step size, multipliers) do not depend on the U width
+    const bool vec64 = c == OP_LZ_BEGIN || c == OP_LZ_STEPS || c == OP_LZ_RITZ || c == OP_LZ_RESTART ||
+                       c == OP_FW_PREP || c == OP_SETP;
+    S.op.R = vec64 ? 0 : S.cur_R;
+    return S.op;
+  }
+};
+
+static bool finite(double x) { return std::isfinite(x); }
+
+struct FistaOut {
+  int status = 0;  // 0 ok, 1 fail, 2 numerical
+  int W = -1;
+  double L = 0, gW = 0, rl2 = 0, vdot = 0, dW2 = 0, wy = 0;
+};
+
+// ADAP-FISTA (Appendix A.1) on psi_s = lam g + 1/2 ||. - x0||^2 over B_tau.
+static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
+  const double mu = 0.5, chi = c.o.chi, sigma = c.o.sigma;
+  double A = 0.0, tk = 1.0, L = L0;
+  int y = x0, x = x0;
+  const int xt = c.alloc(), gr = c.alloc();
+  int z = c.alloc();
+  bool pend = false;
+  double u1 = 0, u2 = 0, u3 = 0;
+  out = FistaOut{};
+  for (int i = 0; i < c.o.fista_max_iter; ++i) {
+    double a = 0, d2 = 0, ypw0 = 0, g_yp = 0;
+    bool accepted = false;
+    for (int bt = 0; bt < 80; ++bt) {
+      a = (tk + std::sqrt(tk * tk + 4.0 * tk * A * (L - mu))) / (2.0 * (L - mu));
+      InstParams &p = c.S.prm;
+      p.cY = A / (A + a);
+      p.cX = a / (A + a);
+      p.lam = lam;
+      p.L = L;
+      p.invL = 1.0 / L;
+      p.upd_x = pend ? 1 : 0;
+      p.u1 = u1;
+      p.u2 = u2;
+      p.u3 = u3;
+      int xn = -1;
+      if (pend) xn = c.alloc();
+      p.buf[RY] = y;
+      p.buf[RX] = x;
+      p.buf[RXT] = xt;
+      p.buf[RW0] = x0;
+      p.buf[RGR] = gr;
+      p.buf[RZ] = z;
+      p.buf[RU2] = pend ? xn : x;
+      c.op(OP_TRIAL);
+      c.S.result.n_fista_trials++;
+      c.S.result.n_sddmm += 2;
+      c.S.result.n_spmm += 1;
+      co_await OpAwait{c.S};
+      if (pend) {
+        if (x != x0 && x != y) c.release(x);
+        x = xn;
+        pend = false;
+      }
+      const double g_xt = c.res(S_G_XT), xtw0 = c.res(S_XTW0), gr_d = c.res(S_GR_D);
+      d2 = c.res(S_D2);
+      ypw0 = c.res(S_YPW0);
+      g_yp = c.res(S_G_YP);
+      if (!finite(g_xt) || !finite(g_yp) || !finite(gr_d) || !finite(d2)) {
+        out.status = 2;
+        goto cleanup;
+      }
+      const double psx = lam * g_xt + 0.5 * xtw0, psy = lam * g_yp + 0.5 * ypw0;
+      if (psx + gr_d + 0.25 * (1.0 - chi) * L * d2 >= psy) {
+        accepted = true;
+        break;
+      }
+      L *= 2.0;
+    }
+    if (!accepted) {
+      out.status = 1;
+      goto cleanup;
+    }
+    {
+      const double A1 = A + a, tk1 = tk + a * mu;
+      u1 = (mu * a + a * (L - mu)) / tk1;
+      u2 = tk / tk1;
+      u3 = -a * (L - mu) / tk1;
+      if (ypw0 < chi * A1 * L * d2) {
+        out.status = 1;
+        goto cleanup;
+      }
+      if ((L - mu) * std::sqrt(d2) <= sigma * std::sqrt(ypw0)) {
+        InstParams &p = c.S.prm;
+        p.buf[RZ] = z;
+        p.buf[RXT] = xt;
+        p.buf[RGR] = gr;
+        p.buf[RW0] = x0;
+        p.lam = lam;
+        p.L = L;
+        c.op(OP_GRAD);
+        c.S.result.n_spmm += 1;
+        co_await OpAwait{c.S};
+        out.status = 0;
+        out.W = z;
+        z = -1;
+        out.L = L;
+        out.gW = g_yp;
+        out.rl2 = c.res(S_RL2);
+        out.dW2 = ypw0;
+        out.vdot = c.res(S_RL_W0) - ypw0;  // <V, x0 - y+> with V = Rl - (x0 - y+)
+        out.wy = c.res(S_WY);
+        goto cleanup;
+      }
+      if (y != x0) c.release(y);
+      y = z;
+      z = c.alloc();
+      pend = true;
+      A = A1;
+      tk = tk1;
+    }
+  }
+  out.status = 1;
+cleanup:
+  c.release(xt);
+  c.release(gr);
+  if (z >= 0) c.release(z);
+  if (y != x0 && y != out.W) c.release(y);
+  if (x != x0 && x != y && x != out.W) c.release(x);
+  co_return;
+}
+
+struct AippOut {
+  int status = 0;  // 0 ok, 1 iter limit, 2 numerical
+  int W = -1;
+  double lam = 0, g = 0;
+};
+
+// ADAP-AIPP (Appendix A): prox-point loop, halving lam on failure.
+static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out) {
+  int Wprev = W0;
+  double gprev = g0, Mbar = 1.0;
+  out = AippOut{};
+  for (int j = 0; j < c.o.aipp_max_iter; ++j) {
+    c.S.result.n_aipp_iters++;
+    FistaOut fo;
+    for (;;) {
+      const double Mj = std::max(1.0, 0.5 * Mbar);
+      co_await fista(c, Wprev, lam, Mj, fo);
+      if (fo.status == 2) {
+        out.status = 2;
+        out.W = Wprev;
+        co_return;
+      }
+      if (fo.status == 0) {
+        const double lhs = lam * gprev - (lam * fo.gW + 0.5 * fo.dW2);
+        if (lhs >= fo.vdot - 1e-13 * (1.0 + std::fabs(lam * gprev))) break;
+        c.release(fo.W);
+      }
+      lam *= 0.5;
+      if (lam < 1e-30) {
+        out.status = 2;
+        out.W = Wprev;
+        co_return;
+      }
+    }
+    const double Rn = std::sqrt(std::max(fo.rl2, 0.0)) / lam;
+    Mbar = fo.L;
+    c.release(Wprev);
+    Wprev = fo.W;
+    gprev = fo.gW;
+    if (Rn <= rho) {
+      out.status = 0;
+      out.W = Wprev;
+      out.lam = lam;
+      out.g = gprev;
+      co_return;
+    }
+  }
+  out.status = 1;
+  out.W = Wprev;
+  out.lam = lam;
+  out.g = gprev;
+}
+
+struct EigOut {
+  double lam = 0, res = 0;
+  int iters = 0, restarts = 0;
+  bool converged = false;
+};
+
+// thick-restart Lanczos with full reorthogonalisation for lambda_min of
+// G = C + A*(yp); the Ritz vector is left in lzv.
+static Task lanczos(Ctx c, double tol_abs, int max_iter, int use_prev, EigOut &out) {
+  Slot &S = c.S;
+  const int kmax = S.kmax;
+  const int LD = KMAX + 1;  // host H: column-major, H[j * LD + i]
+  S.H.assign((size_t)LD * KMAX, 0.0);
+  S.prm.lz_seed = S.seed * 0x9E3779B97F4A7C15ull + (uint64_t)(++S.result.n_eig_calls);
+  S.prm.lz_use_prev = use_prev;
+  S.prm.lz_basis = 0;
+  c.op(OP_LZ_BEGIN);
+  co_await OpAwait{S};
+  int k = 0;
+  out = EigOut{};
+  std::vector<double> Hs, w, Q;
+  for (;;) {
+    const int steps = std::min(8, kmax - k);
+    S.prm.lz_j = k;
+    S.prm.lz_j0 = k;
+    S.prm.lz_steps = steps;
+    PendingOp &op = c.op(OP_LZ_STEPS);
+    op.steps = steps;
+    op.dl_count = (int64_t)steps * (KMAX + 2);
+    co_await OpAwait{S};
+    for (int u = 0; u < steps; ++u) {
+      const int col = k + u;
+      const double *d = S.dl.data() + (size_t)u * (KMAX + 2);
+      for (int i = 0; i <= col; ++i) S.H[(size_t)col * LD + i] = d[i];
+      S.H[(size_t)col * LD + col + 1] = d[KMAX + 1];
+    }
+    k += steps;
+    out.iters += steps;
+    S.result.n_matvec += steps;
+    // Rayleigh-Ritz on the symmetrised projected matrix
+    Hs.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Hs[(size_t)i * k + j] = 0.5 * (S.H[(size_t)j * LD + i] + S.H[(size_t)i * LD + j]);
+    w.assign(k, 0.0);
+    Q.assign((size_t)k * k, 0.0);
+    sym_eig(k, Hs.data(), w.data(), Q.data());
+    const double bk = S.H[(size_t)(k - 1) * LD + k];
+    const bool breakdown = !(bk > 1e-14 * std::max(1.0, std::fabs(w[0])));
+    const double res = breakdown ? 0.0 : std::fabs(bk * Q[(size_t)(k - 1) * k + 0]);
+    out.lam = w[0];
+    out.res = res;
+    const bool conv = res <= std::max(tol_abs, c.o.eig_tol * std::max(1.0, std::fabs(w[0])));
+    if (conv || out.iters >= max_iter || breakdown) {
+      out.converged = conv || breakdown;
+      S.prm.lz_j = k;
+      PendingOp &r = c.op(OP_LZ_RITZ);
+      r.upload.assign((size_t)KMAX * KMAX, 0.0);
+      for (int q = 0; q < k; ++q) r.upload[(size_t)q * KMAX + 0] = Q[(size_t)q * k + 0];
+      co_await OpAwait{S};
+      co_return;
+    }
+    if (k == kmax) {
+      const int qk = std::max(1, std::min(kmax / 2, 16));
+      S.prm.lz_j = k;
+      S.prm.lz_q = qk;
+      PendingOp &r = c.op(OP_LZ_RESTART);
+      r.upload.assign((size_t)KMAX * KMAX, 0.0);
+      for (int q = 0; q < k; ++q)
+        for (int cc = 0; cc < qk; ++cc) r.upload[(size_t)q * KMAX + cc] = Q[(size_t)q * k + cc];
+      co_await OpAwait{S};
+      S.prm.lz_basis ^= 1;
+      std::fill(S.H.begin(), S.H.end(), 0.0);
+      for (int cc = 0; cc < qk; ++cc) {
+        S.H[(size_t)cc * LD + cc] = w[cc];
+        S.H[(size_t)cc * LD + qk] = bk * Q[(size_t)(k - 1) * k + cc];
+      }
+      k = qk;
+      out.restarts++;
+    }
+  }
+}
+
+// Rotate U onto the eigenvectors of U^T U and keep the directions with
+// sigma^2 > drop_tol sigma_max^2 (at most keep_max of them, the largest).
+static Task compress(Ctx c, int &buf, int &r, int keep_max, bool &truncated) {
+  Slot &S = c.S;
+  truncated = false;
+  const int R = S.cur_R;
+  PendingOp &op = c.op(OP_GRAM);
+  op.src = RU;
+  op.dl_count = (int64_t)R * R;
+  S.prm.buf[RU] = buf;
+  co_await OpAwait{S};
+  std::vector<double> G((size_t)r * r), w(r), Q((size_t)r * r);
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) G[(size_t)a * r + b] = S.dl[(size_t)a * R + b];
+  sym_eig(r, G.data(), w.data(), Q.data());
+  const double wmax = std::max(w[r - 1], 0.0);
+  std::vector<int> keep;
+  for (int a = r - 1; a >= 0; --a)
+    if (w[a] > c.o.drop_tol * wmax) keep.push_back(a);
+  if (keep.empty()) keep.push_back(r - 1);
+  if (keep_max > 0 && (int)keep.size() > keep_max) {
+    keep.resize(keep_max);
+    truncated = true;
+  }
+  if ((int)keep.size() == r && !truncated) co_return;
+  const int rnew = (int)keep.size();
+  const int RD = r_bucket(rnew, c.P.prec);
+  const int dst = c.alloc();
+  PendingOp &ro = c.op(OP_ROTATE);
+  ro.R = RD;
+  ro.R2 = R;
+  ro.src = 0;
+  ro.dst = 1;
+  ro.upload.assign((size_t)R_MAX * R_MAX, 0.0);
+  for (int a = 0; a < r; ++a)
+    for (int cc = 0; cc < rnew; ++cc) ro.upload[(size_t)a * R_MAX + cc] = Q[(size_t)a * r + keep[cc]];
+  S.prm.buf[0] = buf;  // role 0 (RX) = source, role 1 (RY) = destination
+  S.prm.buf[1] = dst;
+  S.prm.r = r;
+  S.prm.rnew = rnew;
+  co_await OpAwait{S};
+  c.release(buf);
+  buf = dst;
+  r = rnew;
+  S.cur_R = RD;
+}
+
+static int map_status(int st) {
+  return st;
+}
+
+static Task solve_main(Ctx c) {
+  Slot &S = c.S;
+  const hallar_options &o = c.o;
+  HostProblem &hp = S.hp;
+  const double tau2 = hp.tau2, tau = std::sqrt(tau2);
+  const double t0 = now_s();
+  S.t_start = t0;
+  hallar_result &res = S.result;
+  res.status = HALLAR_E_ITER_LIMIT;
+  double beta = o.beta1;
+  S.prm.beta = beta;
+  // U0 (projected onto the ball B_tau)
+  int U = c.alloc();
+  int r = std::max(1, S.U0r);
+  S.cur_R = r_bucket(r, c.P.prec);
+  {
+    PendingOp &op = c.op(OP_PACK);
+    op.ext = S.U0ext;
+    op.ext_r = S.U0r;
+    op.ext_ld = S.U0r;
+    op.dst = 0;
+    S.prm.buf[0] = U;
+    co_await OpAwait{S};
+    const double nrm2 = c.res(S_NZ);
+    if (nrm2 > tau2) {
+      S.prm.lz_scale = tau / std::sqrt(nrm2);
+      PendingOp &cp = c.op(OP_COPY);
+      cp.src = 0;
+      cp.dst = 0;
+      co_await OpAwait{S};
+    }
+  }
+  auto eval = [&](int buf, int wT, int wyp) {
+    PendingOp &op = c.op(OP_EVAL);
+    op.xrole = RU;
+    op.msel = -1;
+    op.wT = wT;
+    op.wyp = wyp;
+    op.zsel = 0;
+    S.prm.buf[RU] = buf;
+    S.prm.beta = beta;
+    S.result.n_sddmm++;
+  };
+  eval(U, 0, 0);
+  co_await OpAwait{S};
+  double pval_prev = c.res(S_T0);
+  double rnorm_prev = std::sqrt(std::max(c.res(S_RR), 0.0));
+  double lam = o.lam0;
+  double theta = 0.0, pval = 0, dval = 0, pinf = 0, gapr = 0, dinf = 0;
+  bool have_v = false;
+  int t = 0;
+  for (t = 1; t <= o.outer_max_iter; ++t) {
+    const double eps_t = std::max(o.eps1 * std::pow(o.eps_decay, t - 1), o.eps_floor * o.eps) * (1.0 + std::fabs(pval_prev));
+    const double rho = eps_t;
+    eval(U, 0, 0);
+    co_await OpAwait{S};
+    double gY = c.res(S_G_EVAL);
+    bool hlr_ok = false;
+    int Y = -1;
+    double TYT0 = 0, lmin = 0, eres = 0;
+    for (int it = 0; it < o.hlr_max_iter; ++it) {
+      res.n_hlr_iters++;
+      AippOut ao;
+      co_await aipp(c, U, gY, std::min(lam, o.lam0), rho, ao);
+      U = -1;
+      Y = ao.W;
+      lam = ao.lam;
+      if (ao.status != 0) {
+        res.status = ao.status == 2 ? HALLAR_E_NUMERICAL : HALLAR_E_ITER_LIMIT;
+        break;
+      }
+      if (r > 1) {
+        bool tr = false;
+        co_await compress(c, Y, r, 0, tr);
+      }
+      // G = C + A*(p + beta (A(YY^T) - b)) (eq. Grad X Space): T(Y), y'' on device
+      eval(Y, 1, 1);
+      co_await OpAwait{S};
+      TYT0 = c.res(S_T0);
+      const double GYY = c.res(S_T0) + c.res(S_YT);
+      EigOut eo;
+      const double tol_abs = o.eig_frac * eps_t / tau2;
+      co_await lanczos(c, tol_abs, o.eig_max_iter, have_v ? 1 : 0, eo);
+      have_v = true;
+      lmin = eo.lam;
+      eres = eo.res;
+      theta = std::max(-lmin, 0.0);
+      const double gap = GYY + tau2 * theta;
+      if (!finite(gap)) {
+        res.status = HALLAR_E_NUMERICAL;
+        break;
+      }
+      if (gap <= eps_t) {
+        hlr_ok = true;
+        break;
+      }
+      // exact line search (eq. FW stepsize)
+      S.prm.fw_v_on = theta > 0.0 ? 1 : 0;
+      S.prm.tau2 = tau2;
+      c.op(OP_FW_PREP);
+      co_await OpAwait{S};
+      const double den = beta * c.res(S_FWDEN);
+      const double alpha = den > 0.0 ? std::min(gap / den, 1.0) : 1.0;
+      int rnew;
+      if (alpha >= 1.0) {
+        S.prm.fw_col = 0;
+        S.prm.fw_a = 0.0;
+        S.prm.fw_b = theta > 0.0 ? tau : 0.0;
+        rnew = 1;
+      } else if (theta > 0.0) {
+        S.prm.fw_col = r;
+        S.prm.fw_a = std::sqrt(1.0 - alpha);
+        S.prm.fw_b = std::sqrt(alpha) * tau;
+        rnew = r + 1;
+      } else {
+        S.prm.fw_col = -1;
+        S.prm.fw_a = std::sqrt(1.0 - alpha);
+        S.prm.fw_b = 0.0;
+        rnew = r;
+      }
+      const int RD = r_bucket(std::min(rnew, R_MAX), c.P.prec);
+      const int Ynew = c.alloc();
+      PendingOp &fa = c.op(OP_FW_APPLY);
+      fa.R = RD;
+      fa.R2 = S.cur_R;
+      fa.src = 0;
+      fa.dst = 1;
+      S.prm.buf[0] = Y;
+      S.prm.buf[1] = Ynew;
+      S.prm.r = r;
+      co_await OpAwait{S};
+      c.release(Y);
+      Y = -1;
+      U = Ynew;
+      r = rnew;
+      S.cur_R = RD;
+      // at most R_MAX - 1 columns survive a step, so the next one fits R_MAX
+      const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, R_MAX - 1) : R_MAX - 1;
+      if (r > cap) {
+        bool tr = false;
+        co_await compress(c, U, r, cap, tr);
+        if (tr) res.n_truncations++;
+      }
+      eval(U, 0, 0);
+      co_await OpAwait{S};
+      gY = c.res(S_G_EVAL);
+    }
+    if (!hlr_ok) {
+      if (Y >= 0) U = Y;
+      if (res.status == HALLAR_E_ITER_LIMIT && (now_s() - t0) > o.time_limit) res.status = HALLAR_E_TIME_LIMIT;
+      break;
+    }
+    U = Y;
+    // p_t = p + beta (A(U U^T) - b) (eq. dual update SDP Algo 2)
+    c.op(OP_SETP);
+    co_await OpAwait{S};
+    const double bp = c.res(S_BP), rr = c.res(S_RR);
+    pval = TYT0;
+    dval = -bp - tau2 * theta;
+    const double rnorm = std::sqrt(std::max(rr, 0.0));
+    pinf = rnorm / (1.0 + hp.b_l1);
+    gapr = std::fabs(pval - dval) / (1.0 + std::fabs(pval) + std::fabs(dval));
+    const double lamS = (lmin - eres) + theta;
+    dinf = std::max(0.0, -lamS) / (1.0 + hp.c_l1);
+    res.outer_iters = t;
+    if (o.verbose)
+      fprintf(stderr, "[hallar] t=%d beta=%.3g rank=%d pval=%.10g dval=%.10g pinf=%.2e gap=%.2e dinf=%.2e rounds=%lld\n",
+              t, beta, r, pval, dval, pinf, gapr, dinf, (long long)res.n_rounds);
+    if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
+      res.status = HALLAR_OK;
+      break;
+    }
+    if (now_s() - t0 > o.time_limit) {
+      res.status = HALLAR_E_TIME_LIMIT;
+      break;
+    }
+    if (rnorm > o.infeas_ratio * rnorm_prev && pinf > o.pinf_gate * std::max(gapr, dinf))
+      beta = std::min(beta * o.beta_growth, o.beta_max);
+    S.prm.beta = beta;
+    rnorm_prev = rnorm;
+    pval_prev = pval;
+  }
+  if (t > o.outer_max_iter) res.status = HALLAR_E_ITER_LIMIT;
+  res.rank = r;
+  res.pval = pval;
+  res.dval = dval;
+  res.theta = theta;
+  res.pinf = pinf;
+  res.gap = gapr;
+  res.dinf = dinf;
+  res.beta = beta;
+  res.seconds = now_s() - t0;
+  S.final_buf = U;
+  S.final_r = r;
+  S.done = true;
+  (void)map_status;
+}
+
+// coroutine holder so that Task lifetime matches the slot
+void slot_start_solve(Pool &P, int s) {
+  Slot &S = *P.slots[s];
+  S.done = false;
+  S.result = hallar_result{};
+  S.free_bufs.clear();
+  for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);
+  if (S.task) delete S.task;
+  S.task = new Task(solve_main(Ctx{P, S, s, P.opts}));
+  // start: runs until the first device op
+  S.task->h.resume();
+}
+
+hallar_status pool_run(Pool &P, int max_rounds) {
+  int done_rounds = 0;
+  for (;;) {
+    bool did = false;
+    const hallar_status st = run_round(P, did);
+    if (st != HALLAR_OK) {
+      P.fatal = st;
+      return st;
+    }
+    // collect finished
+    for (int s = 0; s < (int)P.slots.size(); ++s) {
+      auto &sp = P.slots[s];
+      if (sp && sp->used && sp->done && sp->task && sp->ticket >= 0) {
+        P.finished.emplace_back(sp->ticket, sp->result);
+        sp->ticket = -2;  // reported
+      }
+    }
+    if (!did) break;
+    if (max_rounds > 0 && ++done_rounds >= max_rounds) break;
+  }
+  return HALLAR_OK;
+}
+
+// ------------------------------------------------------------------ standalone operator calls
+static hallar_status upload_params(Pool &P, int s, hipStream_t st, std::string &err) {
+  // pinned source; the standalone calls always write the same role table
+  P.h_prm[s] = P.slots[s]->prm;
+  HL_TRY(hipMemcpyAsync(P.d_prm + s, P.h_prm + s, sizeof(InstParams), hipMemcpyHostToDevice, st), "params");
+  if (P.insts_dirty) {
+    HL_TRY(hipMemcpyAsync(P.d_insts, P.h_insts.data(), sizeof(InstDev) * P.max_slots, hipMemcpyHostToDevice, st),
+           "descriptors");
+    HL_TRY(hipStreamSynchronize(st), "descriptors");
+    P.insts_dirty = false;
+  }
+  return HALLAR_OK;
+}
+
+static const Tile *slot_tiles(Pool &P, int s) {
+  Slot &S = *P.slots[s];
+  const Layout L = make_layout(S.hp, P.prec, S.Rcap, S.kmax);
+  return (const Tile *)((char *)S.slab + L.tiles);
+}
+static const int32_t *slot_ilist(Pool &P, int s) {
+  Slot &S = *P.slots[s];
+  const Layout L = make_layout(S.hp, P.prec, S.Rcap, S.kmax);
+  return (const int32_t *)((char *)S.slab + L.ilist);
+}
+
+hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st) {
+  Slot &S = *P.slots[s];
+  std::string &err = P.err;
+  const int R = r_bucket(r, P.prec);
+  if (R > S.Rcap) {
+    err = "r exceeds the handle's column capacity";
+    return HALLAR_E_INVALID;
+  }
+  S.prm.buf[RU] = 0;
+  S.prm.beta = 0.0;
+  if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
+  const Tile *T_ = slot_tiles(P, s);
+  const int nt = (int)S.hp.tiles.size();
+  const int32_t *IL = slot_ilist(P, s);
+  const InstDev *D = P.d_insts;
+  op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  op_lr_dots(P.prec, R, st, T_, nt, D, RU);
+  op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0);
+  if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);
+  op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
+  HL_TRY(hipMemcpyAsync(T, &P.d_res[s].v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
+  if (S.hp.m > 0)
+    HL_TRY(hipMemcpyAsync(T + 1, S.dev.TY, sizeof(double) * S.hp.m, hipMemcpyDeviceToDevice, st), "T");
+  HL_TRY(hipGetLastError(), "eval launch");
+  return HALLAR_OK;
+}
+
+hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, int64_t ldu, void *W, int64_t ldw,
+                         hipStream_t st) {
+  Slot &S = *P.slots[s];
+  std::string &err = P.err;
+  const int R = r_bucket(r, P.prec);
+  if (R > S.Rcap) {
+    err = "r exceeds the handle's column capacity";
+    return HALLAR_E_INVALID;
+  }
+  S.prm.buf[RU] = 0;
+  S.prm.buf[RU2] = 1;
+  if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
+  const Tile *T_ = slot_tiles(P, s);
+  const int nt = (int)S.hp.tiles.size();
+  const int32_t *IL = slot_ilist(P, s);
+  const InstDev *D = P.d_insts;
+  op_pairvals(P.prec, st, IL, 1, (int)S.hp.npairs, D, 0, p, S.hp.direct ? 0 : 1);
+  op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  if (S.hp.r0 > 0) {
+    op_lr_dots(P.prec, R, st, T_, nt, D, RU);
+    op_reduce(st, IL, 1, D, RDH_LRONLY, 0, R, 0);
+  }
+  op_spmm(P.prec, R, st, T_, nt, D, RU, 0, 0, RU2, SPM_PLAIN);
+  op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);
+  HL_TRY(hipGetLastError(), "adjoint launch");
+  return HALLAR_OK;
+}
+
+static Task eig_main(Ctx c, double tol, int max_iter, int use_prev, EigOut *out) {
+  co_await lanczos(c, tol, max_iter, use_prev, *out);
+  c.S.done = true;
+}
+
+hallar_status op_min_eig(Pool &P, int s, const double *p, const double *v0, double tol, int max_iter, double *lambda,
+                         double *v, hallar_eig_info *info) {
+  Slot &S = *P.slots[s];
+  std::string &err = P.err;
+  hipStream_t st = P.stream;
+  if (S.hp.m > 0) HL_TRY(hipMemcpyAsync(S.dev.yp, p, sizeof(double) * S.hp.m, hipMemcpyDeviceToDevice, st), "p");
+  if (v0) HL_TRY(hipMemcpyAsync(S.dev.lzv, v0, sizeof(double) * S.hp.n, hipMemcpyDeviceToDevice, st), "v0");
+  HL_TRY(hipStreamSynchronize(st), "sync");
+  EigOut eo;
+  hallar_options o2 = P.opts;
+  o2.eig_tol = tol;
+  S.done = false;
+  if (S.task) delete S.task;
+  S.free_bufs.clear();
+  for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);
+  S.task = new Task(eig_main(Ctx{P, S, s, o2}, 0.0, max_iter, v0 ? 2 : 0, &eo));
+  S.task->h.resume();
+  const hallar_status rs = pool_run(P, 0);
+  if (rs != HALLAR_OK) return rs;
+  delete S.task;
+  S.task = nullptr;
+  *lambda = eo.lam;
+  if (info) {
+    info->iters = eo.iters;
+    info->restarts = eo.restarts;
+    info->residual = eo.res;
+  }
+  if (v) HL_TRY(hipMemcpyAsync(v, S.dev.lzv, sizeof(double) * S.hp.n, hipMemcpyDeviceToDevice, st), "v");
+  HL_TRY(hipStreamSynchronize(st), "sync");
+  return eo.converged ? HALLAR_OK : HALLAR_E_NOT_CONVERGED;
+}
+
+}  // namespace hl

@@ -1,0 +1,85 @@
+// Batched round executor and the pool of resident instances.
+#pragma once
+#include <deque>
+#include <map>
+#include <memory>
+
+#include "host.h"
+
+namespace hl {
+
+// First-fit sub-allocator over one device slab (no hipMalloc while serving).
+class Arena {
+ public:
+  bool init(size_t bytes, std::string &err);
+  void release();
+  // returns offset or SIZE_MAX
+  size_t alloc(size_t bytes);
+  void free(size_t off, size_t bytes);
+  char *base() const { return base_; }
+  size_t capacity() const { return cap_; }
+  size_t used() const { return used_; }
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+};
+
+struct Pool {
+  int prec = 0;
+  hallar_options opts{};
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  bool use_arena = false;  // serving pool: one slab for everything
+  Arena arena;
+  int max_slots = 0;
+  std::vector<std::unique_ptr<Slot>> slots;
+  // device / pinned arrays indexed by slot
+  InstDev *d_insts = nullptr;
+  InstParams *d_prm = nullptr, *h_prm = nullptr;
+  InstRes *d_res = nullptr, *h_res = nullptr;
+  std::vector<InstDev> h_insts;
+  Tile *d_tiles = nullptr, *h_tiles = nullptr;
+  int64_t tiles_cap = 0;
+  int32_t *d_ilist = nullptr, *h_ilist = nullptr;
+  int64_t ilist_cap = 0;
+  double *d_up = nullptr, *h_up = nullptr;
+  int64_t up_cap = 0;
+  double *d_dl = nullptr, *h_dl = nullptr;
+  int64_t dl_cap = 0;
+  bool insts_dirty = true;
+  std::deque<std::pair<int64_t, hallar_result>> finished;
+  int64_t rounds = 0;
+  std::string err;
+  hallar_status fatal = HALLAR_OK;
+};
+
+// lifetime
+hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &opts, hipStream_t stream,
+                        size_t arena_bytes, int64_t tiles_cap, std::string &err);
+void pool_release(Pool &P);
+
+// footprint of an instance (bytes of its device slab)
+size_t instance_bytes(const HostProblem &hp, int prec, int Rcap, int kmax);
+int rcap_for(const hallar_options &o, int prec);
+int kmax_for(const hallar_options &o, int n);
+
+// upload a preprocessed problem into slot `s` (allocates the slab)
+hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err);
+void slot_unload(Pool &P, int s);
+
+// solver: start the coroutine of slot s (U0: device FP64 n x r0 or NULL)
+void slot_start_solve(Pool &P, int s);
+// run rounds until no slot has work or `max_rounds` rounds (<=0: unlimited)
+hallar_status pool_run(Pool &P, int max_rounds);
+int pool_active(const Pool &P);
+
+// standalone operator calls on slot s of P
+hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st);
+hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, int64_t ldu, void *W, int64_t ldw,
+                         hipStream_t st);
+hallar_status op_min_eig(Pool &P, int s, const double *p, const double *v0, double tol, int max_iter, double *lambda,
+                         double *v, hallar_eig_info *info);
+
+}  // namespace hl

@@ -1,0 +1,117 @@
+// Internal layout shared by the host engine and the HIP kernels.
+//
+// Every kernel is "segment indexed": its grid walks a list of Tiles, each a
+// contiguous row range of one instance, and looks the instance up in a
+// device array of InstDev descriptors.  One launch therefore serves one
+// instance (a plain solve) or thousands of uneven ones (batched / served
+// solves) with the same code.  Reductions are deterministic: every tile
+// writes its partial sums to its own slot and a reduce kernel adds the
+// slots of an instance in a fixed order, so an instance's results do not
+// depend on which other instances share the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hl {
+
+constexpr int BLOCK = 256;       // threads per workgroup (4 wave64)
+constexpr int LR_MAX = 2;        // rank of the low-rank objective term
+constexpr int R_MAX = 64;        // columns of U
+constexpr int KMAX = 64;         // Lanczos basis vectors before a restart
+constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR_MAX, >= 3 + LR_MAX * R_MAX)
+constexpr int NRES = 32;         // result scalars per instance
+
+// Roles of the n x R work buffers (operator type).  The host maps roles to
+// physical buffers per instance (InstParams::buf), so FISTA's y <- y+ and
+// similar updates are pointer swaps, not copies.
+enum Role : int { RX = 0, RY, RXT, RW0, RGR, RZ, RU, RU2, NROLE };
+constexpr int NBUF = 8;
+
+struct Tile {
+  int32_t inst;     // index into the InstDev array
+  int32_t row0, row1;
+  int32_t lt;       // tile index inside its instance (partial slot)
+  int8_t plog_u;    // log2 pair streams per row in the SDDMM
+  int8_t plog_s;    // log2 pair streams per row in the SpMM / SpMV
+  int8_t pad_[2];
+};
+
+// Per-instance scalars written by the host before a round.
+struct InstParams {
+  double beta;          // AL penalty
+  double lam, L, invL;  // prox stepsize, FISTA curvature
+  double tau, tau2;
+  double cY, cX;        // x~ = cY * Y + cX * X
+  double u1, u2, u3;    // X <- u1 * Z + u2 * X + u3 * XT (FISTA x update, Z = last y+)
+  double fw_a, fw_b;    // FW: U~ = [fw_a * U, fw_b * v]
+  double lz_scale;      // generic scale
+  int32_t upd_x;
+  int32_t r;            // columns in use
+  int32_t buf[NROLE];   // role -> physical buffer
+  int32_t lz_basis;     // 0: V is the basis, 1: V2
+  int32_t lz_steps;     // Lanczos steps to run this round
+  int32_t lz_j;         // index of the vector the next step multiplies
+  int32_t lz_q;         // Ritz / restart columns
+  int32_t fw_col;       // column receiving the FW direction (-1: none)
+  int32_t fw_rnew;      // columns after the FW step
+  int32_t rnew;         // columns after a rotation
+  int32_t lz_j0;        // lz_j at the start of the round (download layout)
+  int32_t lz_use_prev;  // Lanczos start: previous vector + small noise
+  int32_t fw_v_on;      // Frank-Wolfe direction present (theta > 0)
+  uint64_t lz_seed;     // counter-based start-vector seed
+  int64_t up_off;       // offset of this instance's coefficients in the upload buffer
+  int64_t dl_off;       // offset of this instance's block in the download buffer
+};
+
+// Per-instance scalars written by the kernels, read back by the host.
+struct InstRes {
+  double v[NRES];
+};
+
+// Result slots.
+enum ResSlot : int {
+  S_G_XT = 0, S_G_YP, S_XTW0, S_GR_D, S_D2, S_YPW0, S_NZ, S_PROJC,
+  S_RL2, S_RL_W0, S_WY, S_T0, S_PR, S_RR, S_G_EVAL, S_BP,
+  S_FWDEN, S_LZ_BETA, S_LZ_NRM0, S_LZ_ALPHA, S_GRAM_OK, S_NAN,
+  S_LZ_KV0, S_LZ_KV1,   // K0^T v for the next SpMV (low-rank term)
+  S_YT,                 // sum_l y'_l T_l (G . XX^T = T_0 + sum_l y'_l T_l)
+  S_COUNT
+};
+
+// Device descriptor of one instance.
+struct InstDev {
+  int32_t n, m, npairs, nlower;
+  int32_t r0;           // rank of the low-rank objective term (0: none)
+  int32_t direct;       // every constraint has exactly one pair entry and every pair at most one constraint
+  int32_t ntiles, pad_;
+  // structure (device)
+  const int32_t *rowptr_u, *col_u, *pcon;   // upper CSR over S (pair k = position), constraint of pair (0 = none)
+  const int32_t *rowptr_l, *col_l, *pid_l;  // strictly-lower transpose of S with pair ids
+  const void *c_u, *pa;                     // operator type: C_ij per pair, (A_l)_ij of the pair's constraint
+  const double *c64, *pa64, *b;             // FP64 copies, b (length m)
+  const void *K0; const double *D0;         // low-rank objective: K0 n x r0 (op type), D0 r0 x r0
+  const double *K064;                       // FP64 K0 for the Lanczos SpMV
+  // general (multi-entry) constraints
+  const int32_t *eptr, *econ;               // pair -> entries (constraint id 1..m)
+  const double *ea64, *ew64;                // entry values (A_l)_ij and (2 - delta_ij)(A_l)_ij
+  const int32_t *cptr, *cent;               // constraint -> entry ids (l - 1 indexing)
+  const int32_t *epair;                     // entry -> pair
+  // work buffers
+  void *buf[NBUF];                          // n x R_cap, operator type
+  void *m_xt, *m_yp;                        // pair values of M = C + A*(y') (operator type)
+  double *Bpair;                            // general mode: <U_i,U_j> per pair
+  double *p, *yp, *TY, *Ty;                 // length m
+  double *m64;                              // pair values in FP64 (Lanczos)
+  double *V, *V2;                           // Lanczos bases, (KMAX + 1) x n
+  double *w, *lzv;                          // Lanczos work vector, Ritz / start vector
+  double *hcoef;                            // KMAX + 1 reorthogonalisation coefficients
+  double *Z0;                               // 2 x LR_MAX x R_MAX low-rank products D0 K0^T X
+  const double *up_base;                    // pool upload buffer (Ritz / restart coefficients, rotations)
+  double *dl_base;                          // pool download buffer (Lanczos columns, Gram matrices)
+  double *part;                             // ntiles x PSTRIDE partial sums
+  double *gram;                             // ntiles x R_MAX x R_MAX (compression)
+  InstParams *prm;
+  InstRes *res;
+};
+
+}  // namespace hl

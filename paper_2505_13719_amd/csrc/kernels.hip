@@ -1,0 +1,1379 @@
+// HIP kernels of the HALLaR hot path for gfx950 (CDNA4, wave64).
+//
+// Data layout (per instance, see internal.h):
+//   U-like buffers: n x R row-major, R in {2,4,...,64} zero padded, so one
+//   row is G = R*sizeof(T)/16 aligned 16-byte chunks.  A "group" of G lanes
+//   holds one row; a "team" of G << plog lanes works on one output row with
+//   (1 << plog) pair streams.
+//   Sparse structure: the union support S of the upper-triangle entries
+//   (Section 4.1, eq. def: support S ell) as a row CSR (pair k = position),
+//   and the strictly-lower transpose with pair ids for the symmetric SpMM
+//   (Algorithm 4 uses the pattern S u S^T).
+// Everything here is memory bound: no MFMA (no dense contraction).
+#include "internal.h"
+
+namespace hl {
+
+template <typename T> struct NCh;
+template <> struct NCh<float> { static constexpr int N = 4; };
+template <> struct NCh<double> { static constexpr int N = 2; };
+
+template <typename T>
+struct alignas(16) Chunk {
+  T v[NCh<T>::N];
+};
+
+template <typename T>
+__device__ __forceinline__ Chunk<T> ldc(const T *p) {
+  return *reinterpret_cast<const Chunk<T> *>(p);
+}
+template <typename T>
+__device__ __forceinline__ void stc(T *p, const Chunk<T> &c) {
+  *reinterpret_cast<Chunk<T> *>(p) = c;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor(T v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// sum over aligned groups of W lanes
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = W / 2; o >= 1; o >>= 1) v += shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
+
+// Block reduction of NQ doubles per thread into the tile's partial slots.
+template <int NQ>
+__device__ __forceinline__ void block_partials(double (&acc)[NQ], double *dst) {
+  __shared__ double red[BLOCK / 64][NQ > 0 ? NQ : 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = wave_sum(acc[q]);
+    if (lane == 0) red[wave][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
+    dst[threadIdx.x] = s;
+  }
+}
+
+// Runtime-count variant (count <= PSTRIDE), one value per thread-slot array.
+__device__ __forceinline__ void block_partials_rt(double *acc, int nq, double *dst, double *lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = 0; q < nq; ++q) {
+    double s = wave_sum(acc[q]);
+    if (lane == 0) lds[wave * PSTRIDE + q] = s;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += BLOCK) {
+    double s = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * PSTRIDE + q];
+    dst[q] = s;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T *role_ptr(const InstDev &I, const InstParams &P, int role) {
+  return reinterpret_cast<T *>(I.buf[P.buf[role]]);
+}
+
+// ---------------------------------------------------------------------------
+// SDDMM: T_l = A_l . XX^T over the pairs of S (Algorithm 2, eq. omega:
+// weight (2 - delta_ij) A_ij), T_0 = C . XX^T with the low-rank part
+// Tr(D (K^T X)(K^T X)^T) (Algorithm 3), fused with the augmented-Lagrangian
+// epilogue: r_l = T_l - b_l, y'_l = p_l + beta r_l, partial sums of T_0,
+// p^T r, ||r||^2 and K^T X, and the pair values m_k = C_ij + sum_l y'_l (A_l)_ij
+// of the matrix M = C + A*(y') that the following SpMM multiplies (Alg. 4).
+// ---------------------------------------------------------------------------
+struct SddmmArgs {
+  int32_t xrole;     // input factor
+  int32_t msel;      // 0: m_xt, 1: m_yp, -1: no pair values
+  int32_t write_T;   // store T_l (l >= 1) in TY
+  int32_t write_yp;  // store y'_l in yp
+};
+
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                 SddmmArgs a) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int NQ = 4;  // T0, p^T r, ||r||^2, sum y' T
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
+  constexpr int LOGG = G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
+  const int plog = min((int)tl.plog_u, 6 - LOGG);  // team of G << plog <= 64 lanes
+  const int TS = G << plog;
+  const int team = threadIdx.x / TS;
+  const int lt = threadIdx.x - team * TS;
+  const int strm = lt / G, ch = lt - (lt / G) * G;
+  const int nteams = BLOCK / TS;
+  const T *__restrict__ cu = reinterpret_cast<const T *>(I.c_u);
+  const T *__restrict__ pa = reinterpret_cast<const T *>(I.pa);
+  T *mout = a.msel == 0 ? reinterpret_cast<T *>(I.m_xt) : (a.msel == 1 ? reinterpret_cast<T *>(I.m_yp) : nullptr);
+  const double beta = P.beta;
+  const int direct = I.direct;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+
+  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
+    const Chunk<T> ui = ldc(X + (size_t)i * R + ch * NC);
+    const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
+    for (int k = k0 + strm; k < k1; k += (1 << plog)) {
+      const int j = I.col_u[k];
+      const Chunk<T> uj = ldc(X + (size_t)j * R + ch * NC);
+      T d = T(0);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) d += ui.v[e] * uj.v[e];
+      d = group_sum<G>(d);
+      if (ch == 0) {
+        const double B = (double)d;
+        const double w2 = (i == j) ? 1.0 : 2.0;
+        const double cv = cu ? (double)cu[k] : 0.0;
+        acc[0] += w2 * cv * B;
+        if (direct) {
+          const int l = I.pcon[k];
+          double mv = cv;
+          if (l > 0) {
+            const double av = (double)pa[k];
+            const double t = w2 * av * B;
+            const double r = t - I.b[l - 1];
+            const double pl = I.p[l - 1];
+            const double y = pl + beta * r;
+            acc[1] += pl * r;
+            acc[2] += r * r;
+            acc[3] += y * t;
+            if (a.write_T) I.TY[l - 1] = t;
+            if (a.write_yp) I.yp[l - 1] = y;
+            mv = cv + av * y;
+          }
+          if (mout) mout[k] = (T)mv;
+        } else {
+          I.Bpair[k] = B;
+        }
+      }
+    }
+  }
+  block_partials<NQ>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// K^T X for the low-rank objective term (Algorithm 3: Y_0 = K_0^T U), written
+// to partial slots 4.. of the tile (slots 0..3 belong to k_sddmm).
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_lr_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                   int32_t xrole) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  __shared__ double lds[(BLOCK / 64) * PSTRIDE];
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, xrole);
+  const T *__restrict__ K0 = reinterpret_cast<const T *>(I.K0);
+  const int r0 = I.r0;
+  // thread -> (row offset, chunk); each thread accumulates LR_MAX x NC values
+  double acc[LR_MAX * NC];
+#pragma unroll
+  for (int q = 0; q < LR_MAX * NC; ++q) acc[q] = 0.0;
+  const int ch = threadIdx.x % G;
+  const int rstep = BLOCK / G;
+  for (int i = tl.row0 + threadIdx.x / G; i < tl.row1; i += rstep) {
+    const Chunk<T> u = ldc(X + (size_t)i * R + ch * NC);
+    for (int t = 0; t < r0; ++t) {
+      const double kv = (double)K0[(size_t)i * r0 + t];
+#pragma unroll
+      for (int e = 0; e < NC; ++e) acc[t * NC + e] += kv * (double)u.v[e];
+    }
+  }
+  // reduce lanes with equal chunk index: lanes l and l xor (multiples of G)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < LR_MAX * NC; ++q) {
+    double s = acc[q];
+    for (int o = 32; o >= G; o >>= 1) s += shfl_xor(s, o);
+    acc[q] = s;
+  }
+  // lanes 0..G-1 of each wave hold the per-chunk sums
+  if (lane < G) {
+#pragma unroll
+    for (int q = 0; q < LR_MAX * NC; ++q) {
+      const int t = q / NC, e = q - (q / NC) * NC;
+      lds[wave * PSTRIDE + t * R + lane * NC + e] = acc[q];
+    }
+  }
+  __syncthreads();
+  double *dst = I.part + (size_t)tl.lt * PSTRIDE;
+  for (int q = threadIdx.x; q < r0 * R; q += BLOCK) {
+    double s = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * PSTRIDE + q];
+    dst[4 + q] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// General constraints (a constraint with several pairs or a pair in several
+// constraints): phase B sums the weighted pair products per constraint and
+// applies the AL epilogue; phase C forms the pair values.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_constraints(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                           SddmmArgs a) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  const InstParams &P = *I.prm;
+  const int l = blockIdx.x * BLOCK + threadIdx.x;  // 0-based constraint
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (l < I.m) {
+    double t = 0.0;
+    for (int e = I.cptr[l]; e < I.cptr[l + 1]; ++e) {
+      const int id = I.cent[e];
+      t += I.ew64[id] * I.Bpair[I.epair[id]];  // (2 - delta_ij) (A_l)_ij <U_i, U_j>
+    }
+    const double r = t - I.b[l];
+    const double y = I.p[l] + P.beta * r;
+    acc[0] = I.p[l] * r;
+    acc[1] = r * r;
+    acc[2] = y * t;
+    if (a.write_T) I.TY[l] = t;
+    I.yp[l] = y;
+  }
+  if (blockIdx.x * BLOCK < I.m) block_partials<3>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+}
+
+// pair values m_k = C_ij + sum_{l in L_ij} y_l (A_l)_ij (Algorithm 4)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_pairvals(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                        int32_t msel, int32_t use_yp_ext, const double *__restrict__ yext) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= I.npairs) return;
+  const double *y = use_yp_ext ? yext : I.yp;
+  double mv = I.c64 ? I.c64[k] : 0.0;
+  for (int e = I.eptr[k]; e < I.eptr[k + 1]; ++e) mv += y[I.econ[e] - 1] * I.ea64[e];
+  if (msel == 2) {
+    I.m64[k] = mv;
+  } else {
+    T *m = reinterpret_cast<T *>(msel == 0 ? I.m_xt : I.m_yp);
+    m[k] = (T)mv;
+  }
+}
+
+// Direct-mode pair values from an external or internal multiplier vector
+// (used by the adjoint call and to build the FP64 Lanczos matrix).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_pairvals(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                    int32_t msel, const double *__restrict__ yext) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  const int k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= I.npairs) return;
+  const double *y = yext ? yext : I.yp;
+  double mv = I.c64 ? I.c64[k] : 0.0;
+  const int l = I.pcon[k];
+  if (l > 0) mv += I.pa64[k] * y[l - 1];
+  if (msel == 2) {
+    I.m64[k] = mv;
+  } else {
+    T *m = reinterpret_cast<T *>(msel == 0 ? I.m_xt : I.m_yp);
+    m[k] = (T)mv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SpMM: W = M X + K0 (D0 K0^T X) on the symmetric pattern S u S^T
+// (Algorithms 4 and 5) with epilogues:
+//   PLAIN: store W (role out).
+//   TRIAL: GR = 2 lam W + X - W0 (grad of psi_s = lam g + 1/2||. - W0||^2,
+//          eq. Grad U Space), Z = X - GR / L, partial ||Z||^2.
+//   AIPP:  X = y+, GR = grad psi_s(x~): Rl = 2 lam W - GR + L (XT - X)
+//          = V + W0 - y+ (V of ADAP-FISTA's output), partial ||Rl||^2,
+//          <Rl, W0 - X>, <W, X> (= G . XX^T).
+// ---------------------------------------------------------------------------
+enum SpmmMode : int { SP_PLAIN = 0, SP_TRIAL = 1, SP_AIPP = 2 };
+
+struct SpmmArgs {
+  int32_t xrole;
+  int32_t msel;   // 0: m_xt, 1: m_yp
+  int32_t zsel;   // low-rank product slot
+  int32_t outrole;
+};
+
+template <typename T, int G, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                SpmmArgs a) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int NQ = MODE == SP_AIPP ? 3 : (MODE == SP_TRIAL ? 1 : 1);
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
+  const T *__restrict__ m = reinterpret_cast<const T *>(a.msel ? I.m_yp : I.m_xt);
+  constexpr int LOGG = G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
+  const int plog = min((int)tl.plog_s, 6 - LOGG);
+  const int TS = G << plog;
+  const int team = threadIdx.x / TS;
+  const int lt = threadIdx.x - team * TS;
+  const int strm = lt / G, ch = lt - (lt / G) * G;
+  const int nteams = BLOCK / TS;
+  const int r0 = I.r0;
+  const T *__restrict__ K0 = reinterpret_cast<const T *>(I.K0);
+  const double *Z0 = I.Z0 + a.zsel * LR_MAX * R_MAX;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  const T lam2 = (T)(2.0 * P.lam), invL = (T)P.invL, Lc = (T)P.L;
+
+  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
+    T w[NC];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) w[e] = T(0);
+    const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
+    for (int k = k0 + strm; k < k1; k += (1 << plog)) {
+      const int j = I.col_u[k];
+      const T mv = m[k];
+      const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += mv * x.v[e];
+    }
+    const int e0 = I.rowptr_l[i], e1 = I.rowptr_l[i + 1];
+    for (int e2 = e0 + strm; e2 < e1; e2 += (1 << plog)) {
+      const int j = I.col_l[e2];
+      const T mv = m[I.pid_l[e2]];
+      const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += mv * x.v[e];
+    }
+    // reduce the pair streams (lanes ch + G*s)
+    for (int o = TS / 2; o >= G; o >>= 1) {
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
+    }
+    if (strm == 0) {
+      for (int t = 0; t < r0; ++t) {
+        const T kv = K0[(size_t)i * r0 + t];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) w[e] += kv * (T)Z0[t * R_MAX + ch * NC + e];
+      }
+      const size_t off = (size_t)i * R + ch * NC;
+      if (MODE == SP_PLAIN) {
+        Chunk<T> o;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) o.v[e] = w[e];
+        stc(role_ptr<T>(I, P, a.outrole) + off, o);
+      } else if (MODE == SP_TRIAL) {
+        const Chunk<T> xi = ldc(X + off);
+        const Chunk<T> w0 = ldc(role_ptr<T>(I, P, RW0) + off);
+        Chunk<T> gr, z;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) {
+          gr.v[e] = lam2 * w[e] + (xi.v[e] - w0.v[e]);
+          z.v[e] = xi.v[e] - gr.v[e] * invL;
+          acc[0] += (double)z.v[e] * (double)z.v[e];
+        }
+        stc(role_ptr<T>(I, P, RGR) + off, gr);
+        stc(role_ptr<T>(I, P, RZ) + off, z);
+      } else {
+        const Chunk<T> xi = ldc(X + off);
+        const Chunk<T> gr = ldc(role_ptr<T>(I, P, RGR) + off);
+        const Chunk<T> xt = ldc(role_ptr<T>(I, P, RXT) + off);
+        const Chunk<T> w0 = ldc(role_ptr<T>(I, P, RW0) + off);
+#pragma unroll
+        for (int e = 0; e < NC; ++e) {
+          const double rl = (double)(lam2 * w[e] - gr.v[e] + Lc * (xt.v[e] - xi.v[e]));
+          acc[0] += rl * rl;
+          acc[1] += rl * (double)(w0.v[e] - xi.v[e]);
+          acc[2] += (double)w[e] * (double)xi.v[e];
+        }
+      }
+    }
+  }
+  if (MODE != SP_PLAIN) block_partials<NQ>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels over the rows of a tile (G chunks per row).
+// ---------------------------------------------------------------------------
+// FISTA extrapolation: optionally X <- u1 Y + u2 X + u3 XT (x_{i+1} of the
+// previous accepted trial, Y = y_{i+1}, s = (L - mu)(x~ - y+) folded in), then
+// XT = cY Y + cX X; partial ||XT - W0||^2.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *Xp = role_ptr<T>(I, P, RX);
+  T *XNp = role_ptr<T>(I, P, RU2);  // updated x (a different buffer than RX)
+  const T *Yp = role_ptr<T>(I, P, RY);
+  T *XTp = role_ptr<T>(I, P, RXT);
+  const T *W0p = role_ptr<T>(I, P, RW0);
+  const T cY = (T)P.cY, cX = (T)P.cX, u1 = (T)P.u1, u2 = (T)P.u2, u3 = (T)P.u3;
+  const int upd = P.upd_x;
+  double acc[1] = {0.0};
+  const int total = (tl.row1 - tl.row0) * G;
+  const size_t base = (size_t)tl.row0 * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const size_t off = base + (size_t)t * NC;
+    Chunk<T> x = ldc(Xp + off);
+    const Chunk<T> y = ldc(Yp + off), w0 = ldc(W0p + off);
+    if (upd) {
+      const Chunk<T> xt = ldc(XTp + off);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) x.v[e] = u1 * y.v[e] + u2 * x.v[e] + u3 * xt.v[e];
+      stc(XNp + off, x);
+    }
+    Chunk<T> o;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      o.v[e] = cY * y.v[e] + cX * x.v[e];
+      const double d = (double)o.v[e] - (double)w0.v[e];
+      acc[0] += d * d;
+    }
+    stc(XTp + off, o);
+  }
+  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// y+ = c Z (projection onto the Frobenius ball, c from the reduce kernel),
+// partials <GR, y+ - XT>, ||y+ - XT||^2, ||y+ - W0||^2.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  T *Zp = role_ptr<T>(I, P, RZ);
+  const T *XTp = role_ptr<T>(I, P, RXT);
+  const T *GRp = role_ptr<T>(I, P, RGR);
+  const T *W0p = role_ptr<T>(I, P, RW0);
+  const T c = (T)I.res->v[S_PROJC];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int total = (tl.row1 - tl.row0) * G;
+  const size_t base = (size_t)tl.row0 * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const size_t off = base + (size_t)t * NC;
+    Chunk<T> z = ldc(Zp + off);
+    const Chunk<T> xt = ldc(XTp + off), gr = ldc(GRp + off), w0 = ldc(W0p + off);
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      z.v[e] = c * z.v[e];
+      const double d = (double)z.v[e] - (double)xt.v[e];
+      const double f = (double)z.v[e] - (double)w0.v[e];
+      acc[0] += (double)gr.v[e] * d;
+      acc[1] += d * d;
+      acc[2] += f * f;
+    }
+    stc(Zp + off, z);
+  }
+  block_partials<3>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// Copy role src -> role dst (scaled), optional partial ||dst||^2.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_copy_scale(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                      int32_t src, int32_t dst) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *S = role_ptr<T>(I, P, src);
+  T *D = role_ptr<T>(I, P, dst);
+  const T c = (T)P.lz_scale;
+  double acc[1] = {0.0};
+  const int total = (tl.row1 - tl.row0) * G;
+  const size_t base = (size_t)tl.row0 * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const size_t off = base + (size_t)t * NC;
+    Chunk<T> x = ldc(S + off);
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      x.v[e] *= c;
+      acc[0] += (double)x.v[e] * (double)x.v[e];
+    }
+    stc(D + off, x);
+  }
+  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// Pack an external n x r (ld) FP64/op-type matrix into role dst (R columns,
+// zero padded) and optionally scale; partial ||dst||^2.
+template <typename T, int G, typename S>
+__global__ __launch_bounds__(BLOCK) void k_pack(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                const S *__restrict__ src, int32_t r, int64_t ld, int32_t dst, double scale) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  T *D = role_ptr<T>(I, P, dst);
+  double acc[1] = {0.0};
+  const int total = (tl.row1 - tl.row0) * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const int i = tl.row0 + t / R, c = t % R;
+    const T v = c < r ? (T)(scale * (double)src[(size_t)i * ld + c]) : T(0);
+    D[(size_t)i * R + c] = v;
+    acc[0] += (double)v * (double)v;
+  }
+  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+template <typename T, int G, typename S>
+__global__ __launch_bounds__(BLOCK) void k_unpack(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                  S *__restrict__ out, int32_t r, int64_t ld, int32_t src) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *Sx = role_ptr<T>(I, P, src);
+  const int total = (tl.row1 - tl.row0) * r;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const int i = tl.row0 + t / r, c = t % r;
+    out[(size_t)i * ld + c] = (S)Sx[(size_t)i * R + c];
+  }
+}
+
+// Frank-Wolfe update in U-space (eq. tilde Y Algo 2): dst[:, :r] = fw_a src,
+// dst[:, fw_col] = fw_b v, zero padding up to the destination width RD.
+template <typename T, int GS, int GD>
+__global__ __launch_bounds__(BLOCK) void k_fw_apply(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                    int32_t src, int32_t dst) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int RS = GS * NC, RD = GD * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *S = role_ptr<T>(I, P, src);
+  T *D = role_ptr<T>(I, P, dst);
+  const T fa = (T)P.fw_a;
+  const double fb = P.fw_b;
+  const int r = P.r, col = P.fw_col;
+  const double *v = I.lzv;
+  const int total = (tl.row1 - tl.row0) * RD;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const int i = tl.row0 + t / RD, c = t % RD;
+    T val = T(0);
+    if (c == col) val = (T)(fb * v[i]);
+    else if (c < r && c < RS && col != 0) val = fa * S[(size_t)i * RS + c];
+    D[(size_t)i * RD + c] = val;
+  }
+}
+
+// Gram partials X^T X (compression of U, R x R per tile).
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_gram(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                int32_t src) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int RB = 16;  // rows staged per step
+  __shared__ double rows[RB][R];
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *S = role_ptr<T>(I, P, src);
+  constexpr int PER = (R * R + BLOCK - 1) / BLOCK;
+  double acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+  for (int i0 = tl.row0; i0 < tl.row1; i0 += RB) {
+    const int nr = min(RB, tl.row1 - i0);
+    for (int t = threadIdx.x; t < RB * R; t += BLOCK) {
+      const int rr = t / R, c = t % R;
+      rows[rr][c] = rr < nr ? (double)S[(size_t)(i0 + rr) * R + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * BLOCK;
+      if (idx < R * R) {
+        const int a = idx / R, b = idx % R;
+        double s = 0.0;
+        for (int rr = 0; rr < RB; ++rr) s += rows[rr][a] * rows[rr][b];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+  double *dst = I.gram + (size_t)tl.lt * R * R;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * BLOCK;
+    if (idx < R * R) dst[idx] = acc[q];
+  }
+}
+
+// dst[:, :rnew] = src[:, :r] Q (Q: R_MAX stride, column c of the new basis).
+template <typename T, int GS, int GD>
+__global__ __launch_bounds__(BLOCK) void k_rotate(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                  int32_t src, int32_t dst) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int RS = GS * NC, RD = GD * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *S = role_ptr<T>(I, P, src);
+  T *D = role_ptr<T>(I, P, dst);
+  const int r = P.r, rnew = P.rnew;
+  const double *Q = I.up_base + P.up_off;
+  const int total = (tl.row1 - tl.row0) * RD;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const int i = tl.row0 + t / RD, c = t % RD;
+    double s = 0.0;
+    if (c < rnew)
+      for (int a = 0; a < r; ++a) s += (double)S[(size_t)i * RS + a] * Q[a * R_MAX + c];
+    D[(size_t)i * RD + c] = (T)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Frank-Wolfe step size: T(v v^T)_l for the constraints and the partial
+// sum of (T(YY^T)_l - tau^2 T(vv^T)_l)^2 (denominator of eq. FW stepsize).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_fw_den(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const double *v = I.lzv;
+  const double tau2 = P.tau2;
+  double acc[1] = {0.0};
+  const int k0 = I.rowptr_u[tl.row0], k1 = I.rowptr_u[tl.row1];
+  // pair -> row by a per-row walk: each thread takes pairs of rows
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) {
+    const double vi = v[i];
+    for (int k = I.rowptr_u[i]; k < I.rowptr_u[i + 1]; ++k) {
+      const int j = I.col_u[k];
+      const double w2 = (i == j) ? 1.0 : 2.0;
+      if (I.direct) {
+        const int l = I.pcon[k];
+        if (l > 0) {
+          const double t = P.fw_v_on ? w2 * I.pa64[k] * vi * v[j] : 0.0;
+          I.Ty[l - 1] = t;
+          const double d = I.TY[l - 1] - tau2 * t;
+          acc[0] += d * d;
+        }
+      } else {
+        I.Bpair[k] = P.fw_v_on ? vi * v[j] : 0.0;
+      }
+    }
+  }
+  (void)k0; (void)k1;
+  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// general-mode denominator (per constraint)
+__global__ __launch_bounds__(BLOCK) void k_fw_den_gen(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  const InstParams &P = *I.prm;
+  const int l = blockIdx.x * BLOCK + threadIdx.x;
+  double acc[1] = {0.0};
+  if (l < I.m) {
+    double t = 0.0;
+    for (int e = I.cptr[l]; e < I.cptr[l + 1]; ++e) {
+      const int id = I.cent[e];
+      t += I.ew64[id] * I.Bpair[I.epair[id]];
+    }
+    I.Ty[l] = t;
+    const double d = I.TY[l] - P.tau2 * t;
+    acc[0] = d * d;
+  }
+  if (blockIdx.x * BLOCK < I.m) block_partials<1>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+}
+
+// p <- y'(Y) and partial b^T p (dual value), ||T(Y) - b||^2.
+__global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  const int l = blockIdx.x * BLOCK + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (l < I.m) {
+    const double y = I.yp[l];
+    I.p[l] = y;
+    acc[0] = I.b[l] * y;
+    const double r = I.TY[l] - I.b[l];
+    acc[1] = r * r;
+  }
+  if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos (FP64).  Basis rows V[q * n + i]; w is the work vector.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double *lz_basis(const InstDev &I, const InstParams &P) { return P.lz_basis ? I.V2 : I.V; }
+
+// w = G v_j with G = C + A*(y) in FP64 (pair values m64) plus the low-rank
+// term K0 D0 (K0^T v_j); partial v_j^T w is not needed (dots follow).
+__global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                   int32_t from_lzv) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  if (!from_lzv && P.lz_steps <= 0) return;
+  const double *v = from_lzv ? I.lzv : lz_basis(I, P) + (size_t)P.lz_j * I.n;
+  const int plog = tl.plog_s;
+  const int TS = 1 << plog;
+  const int team = threadIdx.x >> plog;
+  const int strm = threadIdx.x & (TS - 1);
+  const int nteams = BLOCK >> plog;
+  double kd[LR_MAX] = {0.0, 0.0};
+  for (int t = 0; t < I.r0; ++t) {
+    double s = 0.0;
+    for (int u = 0; u < I.r0; ++u) s += I.D0[t * I.r0 + u] * I.res->v[S_LZ_KV0 + u];
+    kd[t] = s;
+  }
+  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
+    double w = 0.0;
+    for (int k = I.rowptr_u[i] + strm; k < I.rowptr_u[i + 1]; k += TS) w += I.m64[k] * v[I.col_u[k]];
+    for (int e = I.rowptr_l[i] + strm; e < I.rowptr_l[i + 1]; e += TS) w += I.m64[I.pid_l[e]] * v[I.col_l[e]];
+    for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
+    if (strm == 0) {
+      for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
+      I.w[i] = w;
+    }
+  }
+}
+
+// partial dots: q < nq: <V_q, w>; if lr: K0^T w at slots nq.. (only for the final pass)
+__global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  __shared__ double lds[(BLOCK / 64) * PSTRIDE];
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  if (P.lz_steps <= 0) return;
+  const double *V = lz_basis(I, P);
+  const int nq = P.lz_j + 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t n = I.n;
+  // each wave takes groups of 8 basis vectors; lanes stride over rows
+  constexpr int QB = 8;
+  for (int q0 = wave * QB; q0 < nq; q0 += (BLOCK / 64) * QB) {
+    double acc[QB];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) acc[u] = 0.0;
+    for (int i = tl.row0 + lane; i < tl.row1; i += 64) {
+      const double wi = I.w[i];
+#pragma unroll
+      for (int u = 0; u < QB; ++u)
+        if (q0 + u < nq) acc[u] += V[(size_t)(q0 + u) * n + i] * wi;
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      const double s = wave_sum(acc[u]);
+      if (lane == 0 && q0 + u < nq) lds[q0 + u] = s;
+    }
+  }
+  __syncthreads();
+  double *dst = I.part + (size_t)tl.lt * PSTRIDE;
+  for (int q = threadIdx.x; q < nq; q += BLOCK) dst[q] = lds[q];
+}
+
+// w -= sum_q V_q h_q; in the final pass also partial ||w||^2 and K0^T w.
+__global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                     int32_t final_pass) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  if (P.lz_steps <= 0) return;
+  const double *V = lz_basis(I, P);
+  const int nq = P.lz_j + 1;
+  const size_t n = I.n;
+  __shared__ double h[KMAX + 1];
+  for (int q = threadIdx.x; q < nq; q += BLOCK) h[q] = I.hcoef[q];
+  __syncthreads();
+  double acc[1 + LR_MAX] = {0.0, 0.0, 0.0};
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) {
+    double wi = I.w[i];
+    for (int q = 0; q < nq; ++q) wi -= V[(size_t)q * n + i] * h[q];
+    I.w[i] = wi;
+    if (final_pass) {
+      acc[0] += wi * wi;
+      for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
+    }
+  }
+  if (final_pass) block_partials<1 + LR_MAX>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// v_{j+1} = w / beta_j (beta from the reduce kernel)
+__global__ __launch_bounds__(BLOCK) void k_lz_scale(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  if (P.lz_steps < 0) return;
+  // the reduce kernel already advanced lz_j; the new vector index is lz_j
+  double *V = lz_basis(I, P);
+  const double b = I.res->v[S_LZ_BETA];
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  const int j = P.lz_j;
+  if (j > KMAX) return;
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) V[(size_t)j * I.n + i] = I.w[i] * inv;
+}
+
+// start vector: w = lzv (written by the host-side generator kernel), partial
+// ||w||^2 and K0^T w.
+__global__ __launch_bounds__(BLOCK) void k_lz_start(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const uint64_t seed = P.lz_seed;
+  const int use_prev = P.lz_use_prev;
+  double acc[1 + LR_MAX] = {0.0, 0.0, 0.0};
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) {
+    // counter-based Gaussian: splitmix64 of (seed, i), Box-Muller
+    uint64_t z = seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(i + 1));
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u1 = ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    uint64_t z2 = z * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z2 = (z2 ^ (z2 >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z2 = (z2 ^ (z2 >> 27)) * 0x94D049BB133111EBull;
+    z2 ^= z2 >> 31;
+    const double u2 = ((z2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    const double wi = use_prev == 2 ? I.lzv[i] : (use_prev ? I.lzv[i] + 1e-2 * g / sqrt((double)I.n) : g);
+    I.w[i] = wi;
+    acc[0] += wi * wi;
+    for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
+  }
+  block_partials<1 + LR_MAX>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+}
+
+// V[dst] = sum_{q < nq} Vsrc_q S[q, c] for c < ncol (Ritz vectors / thick restart),
+// writing either the other basis (restart) or lzv (single Ritz vector).
+__global__ __launch_bounds__(BLOCK) void k_lz_combine(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                      int32_t to_lzv) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const double *Vs = lz_basis(I, P);
+  double *Vd = P.lz_basis ? I.V : I.V2;
+  const int nq = P.lz_j;  // basis vectors v_0..v_{k-1}
+  const int ncol = to_lzv ? 1 : P.lz_q;
+  const size_t n = I.n;
+  const double *S = I.up_base + P.up_off;
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) {
+    for (int c = 0; c < ncol; ++c) {
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += Vs[(size_t)q * n + i] * S[q * KMAX + c];
+      if (to_lzv) I.lzv[i] = s;
+      else Vd[(size_t)c * n + i] = s;
+    }
+    if (!to_lzv) Vd[(size_t)ncol * n + i] = Vs[(size_t)nq * n + i];  // residual direction v_k
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: one block per instance sums that instance's tile partials in a
+// fixed order and applies the op's scalar epilogue.
+// ---------------------------------------------------------------------------
+enum RedOp : int {
+  RD_COMBO = 0,    // ||XT - W0||^2
+  RD_SDDMM_XT,     // g(XT), Z0 slot 0
+  RD_TRIAL_PROJ,   // ||Z||^2 -> projection factor
+  RD_PROJ_DOTS,    // <GR, d>, ||d||^2, ||y+ - W0||^2
+  RD_SDDMM_YP,     // g(y+), Z0 slot 1
+  RD_AIPP,         // ||Rl||^2, <Rl, W0 - y+>, <W, y+>
+  RD_EVAL,         // g at an evaluation point, T0, p^T r, ||r||^2
+  RD_LRONLY,       // K0^T X -> Z0 slot (zsel 0)
+  RD_LZ_START,     // ||w||, K0^T w -> normalise into V_0
+  RD_LZ_H1,        // h1 -> hcoef, H column
+  RD_LZ_H2,        // h2 -> hcoef, H column += h2
+  RD_LZ_FINAL,     // beta_j, K0^T v_{j+1}, j++
+  RD_FW_DEN,       // sum (T_Y - tau2 T_v)^2
+  RD_SETP,         // b^T p, ||r||^2 (constraint-major partials)
+  RD_NORM,         // ||.||^2 of a pack / copy
+  RD_GEN_EXTRA,    // general mode: add constraint-major p^T r, ||r||^2 rows
+  RD_GRAM          // sum gram partials
+};
+
+struct RedArgs {
+  int32_t op;
+  int32_t zsel;
+  int32_t R;      // current width (for K^T X slots / gram)
+  int32_t extra;  // number of constraint-major partial rows (general mode / set_p)
+};
+
+__device__ double sum_slot(const InstDev &I, int q, int first, int count, double *lds) {
+  // fixed-order block sum of part[(first + t) * PSTRIDE + q], t < count
+  double s = 0.0;
+  for (int t = threadIdx.x; t < count; t += BLOCK) s += I.part[(size_t)(first + t) * PSTRIDE + q];
+  s = wave_sum(s);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) lds[wave] = s;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < BLOCK / 64; ++w) tot += lds[w];
+  return tot;
+}
+
+__device__ void lowrank_finish(const InstDev &I, int R, int zsel, double *lds, double *trace_out) {
+  // Y0 (r0 x R) from slots 3.., Z0 = D0 Y0, trace = Tr(D0 Y0 Y0^T)
+  const int r0 = I.r0;
+  double *Z0 = I.Z0 + zsel * LR_MAX * R_MAX;
+  __shared__ double y0[LR_MAX * R_MAX];
+  for (int q = 0; q < r0 * R; ++q) {
+    const double s = sum_slot(I, 4 + q, 0, I.ntiles, lds);
+    if (threadIdx.x == 0) y0[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0;
+    for (int t = 0; t < r0; ++t)
+      for (int u = 0; u < r0; ++u) {
+        double d = 0.0;
+        for (int c = 0; c < R; ++c) d += y0[t * R + c] * y0[u * R + c];
+        tr += I.D0[t * r0 + u] * d;
+      }
+    for (int t = 0; t < r0; ++t)
+      for (int c = 0; c < R_MAX; ++c) {
+        double s = 0.0;
+        if (c < R)
+          for (int u = 0; u < r0; ++u) s += I.D0[t * r0 + u] * y0[u * R + c];
+        Z0[t * R_MAX + c] = s;
+      }
+    *trace_out = tr;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                  RedArgs a) {
+  __shared__ double lds[BLOCK / 64];
+  __shared__ double tr;
+  const InstDev &I = insts[ilist[blockIdx.x]];
+  InstParams &P = *I.prm;
+  double *res = I.res->v;
+  const int nt = I.ntiles;
+  switch (a.op) {
+    case RD_COMBO: {
+      const double s = sum_slot(I, 0, 0, nt, lds);
+      if (threadIdx.x == 0) res[S_XTW0] = s;
+      break;
+    }
+    case RD_SDDMM_XT:
+    case RD_SDDMM_YP:
+    case RD_EVAL: {
+      double T0 = sum_slot(I, 0, 0, nt, lds);
+      double pr = sum_slot(I, 1, 0, nt, lds);
+      double rr = sum_slot(I, 2, 0, nt, lds);
+      double yt = sum_slot(I, 3, 0, nt, lds);
+      const int ex = I.direct ? 0 : (I.m + BLOCK - 1) / BLOCK;
+      if (ex > 0) {
+        pr += sum_slot(I, 0, nt, ex, lds);
+        rr += sum_slot(I, 1, nt, ex, lds);
+        yt += sum_slot(I, 2, nt, ex, lds);
+      }
+      if (threadIdx.x == 0) tr = 0.0;
+      __syncthreads();
+      if (I.r0 > 0) lowrank_finish(I, a.R, a.op == RD_SDDMM_YP ? 1 : a.zsel, lds, &tr);
+      if (threadIdx.x == 0) {
+        const double t0 = T0 + tr;
+        const double g = t0 + pr + 0.5 * P.beta * rr;
+        const int slot = a.op == RD_SDDMM_XT ? S_G_XT : (a.op == RD_SDDMM_YP ? S_G_YP : S_G_EVAL);
+        res[slot] = g;
+        if (a.op == RD_EVAL) {
+          res[S_T0] = t0;
+          res[S_PR] = pr;
+          res[S_RR] = rr;
+          res[S_YT] = yt;
+        }
+        if (!(g == g) || g - g != 0.0) res[S_NAN] = 1.0;
+      }
+      break;
+    }
+    case RD_TRIAL_PROJ: {
+      const double nz = sum_slot(I, 0, 0, nt, lds);
+      if (threadIdx.x == 0) {
+        res[S_NZ] = nz;
+        res[S_PROJC] = nz > P.tau2 ? P.tau / sqrt(nz) : 1.0;
+      }
+      break;
+    }
+    case RD_PROJ_DOTS: {
+      const double a0 = sum_slot(I, 0, 0, nt, lds);
+      const double a1 = sum_slot(I, 1, 0, nt, lds);
+      const double a2 = sum_slot(I, 2, 0, nt, lds);
+      if (threadIdx.x == 0) {
+        res[S_GR_D] = a0;
+        res[S_D2] = a1;
+        res[S_YPW0] = a2;
+      }
+      break;
+    }
+    case RD_AIPP: {
+      const double a0 = sum_slot(I, 0, 0, nt, lds);
+      const double a1 = sum_slot(I, 1, 0, nt, lds);
+      const double a2 = sum_slot(I, 2, 0, nt, lds);
+      if (threadIdx.x == 0) {
+        res[S_RL2] = a0;
+        res[S_RL_W0] = a1;
+        res[S_WY] = a2;
+      }
+      break;
+    }
+    case RD_LRONLY: {
+      if (I.r0 > 0) lowrank_finish(I, a.R, a.zsel, lds, &tr);
+      break;
+    }
+    case RD_NORM: {
+      const double s = sum_slot(I, 0, 0, nt, lds);
+      if (threadIdx.x == 0) res[S_NZ] = s;
+      break;
+    }
+    case RD_LZ_START: {
+      const double nrm2 = sum_slot(I, 0, 0, nt, lds);
+      double kw[LR_MAX] = {0.0, 0.0};
+      for (int t = 0; t < I.r0; ++t) kw[t] = sum_slot(I, 1 + t, 0, nt, lds);
+      if (threadIdx.x == 0) {
+        const double b = sqrt(nrm2);
+        res[S_LZ_BETA] = b;
+        res[S_LZ_NRM0] = b;
+        for (int t = 0; t < I.r0; ++t) res[S_LZ_KV0 + t] = b > 0 ? kw[t] / b : 0.0;
+        P.lz_j = 0;
+      }
+      break;
+    }
+    case RD_LZ_H1:
+    case RD_LZ_H2: {
+      if (P.lz_steps <= 0) break;
+      const int nq = P.lz_j + 1;
+      // thread q sums slot q over tiles (fixed order)
+      double *Hc = I.dl_base + P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2);
+      for (int q = threadIdx.x; q < nq; q += BLOCK) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += I.part[(size_t)t * PSTRIDE + q];
+        I.hcoef[q] = s;
+        if (a.op == RD_LZ_H1) Hc[q] = s;
+        else Hc[q] += s;
+      }
+      break;
+    }
+    case RD_LZ_FINAL: {
+      if (P.lz_steps <= 0) break;
+      const double nrm2 = sum_slot(I, 0, 0, nt, lds);
+      double kw[LR_MAX] = {0.0, 0.0};
+      for (int t = 0; t < I.r0; ++t) kw[t] = sum_slot(I, 1 + t, 0, nt, lds);
+      if (threadIdx.x == 0) {
+        const double b = sqrt(nrm2);
+        res[S_LZ_BETA] = b;
+        I.dl_base[P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2) + KMAX + 1] = b;
+        for (int t = 0; t < I.r0; ++t) res[S_LZ_KV0 + t] = b > 0 ? kw[t] / b : 0.0;
+        P.lz_j += 1;
+        P.lz_steps -= 1;
+      }
+      break;
+    }
+    case RD_FW_DEN: {
+      double s = sum_slot(I, 0, 0, nt, lds);
+      if (!I.direct) s += sum_slot(I, 0, nt, (I.m + BLOCK - 1) / BLOCK, lds);
+      if (threadIdx.x == 0) res[S_FWDEN] = s;
+      break;
+    }
+    case RD_SETP: {
+      const int ex = (I.m + BLOCK - 1) / BLOCK;
+      const double bp = sum_slot(I, 0, nt, ex, lds);
+      const double rr = sum_slot(I, 1, nt, ex, lds);
+      if (threadIdx.x == 0) {
+        res[S_BP] = bp;
+        res[S_RR] = rr;
+      }
+      break;
+    }
+    case RD_GRAM: {
+      const int R = a.R;
+      for (int q = threadIdx.x; q < R * R; q += BLOCK) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += I.gram[(size_t)t * R * R + q];
+        I.dl_base[P.dl_off + q] = s;  // Gram matrix, row-major R x R
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Lanczos start: V_0 = w / ||w||
+__global__ __launch_bounds__(BLOCK) void k_lz_first(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  double *V = lz_basis(I, P);
+  const double b = I.res->v[S_LZ_BETA];
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  for (int i = tl.row0 + threadIdx.x; i < tl.row1; i += BLOCK) V[i] = I.w[i] * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+constexpr int g_of(int R) {
+  return R * (int)sizeof(T) / 16;
+}
+
+#define HL_DISPATCH_G(T, R, FN, ...)                        \
+  do {                                                      \
+    switch (g_of<T>(R)) {                                   \
+      case 1: FN<T, 1>(__VA_ARGS__); break;                 \
+      case 2: FN<T, 2>(__VA_ARGS__); break;                 \
+      case 4: FN<T, 4>(__VA_ARGS__); break;                 \
+      case 8: FN<T, 8>(__VA_ARGS__); break;                 \
+      case 16: FN<T, 16>(__VA_ARGS__); break;               \
+      case 32: if constexpr (sizeof(T) == 8) { FN<T, 32>(__VA_ARGS__); } break; \
+      default: break;                                       \
+    }                                                       \
+  } while (0)
+
+template <typename T, int G>
+static void l_sddmm(hipStream_t s, const Tile *t, int nt, const InstDev *d, SddmmArgs a) {
+  hipLaunchKernelGGL((k_sddmm<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d, a);
+}
+template <typename T, int G>
+static void l_lrdots(hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole) {
+  hipLaunchKernelGGL((k_lr_dots<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
+}
+template <typename T, int G>
+static void l_spmm(hipStream_t s, const Tile *t, int nt, const InstDev *d, SpmmArgs a, int mode) {
+  if (mode == SP_PLAIN) hipLaunchKernelGGL((k_spmm<T, G, SP_PLAIN>), dim3(nt), dim3(BLOCK), 0, s, t, d, a);
+  else if (mode == SP_TRIAL) hipLaunchKernelGGL((k_spmm<T, G, SP_TRIAL>), dim3(nt), dim3(BLOCK), 0, s, t, d, a);
+  else hipLaunchKernelGGL((k_spmm<T, G, SP_AIPP>), dim3(nt), dim3(BLOCK), 0, s, t, d, a);
+}
+template <typename T, int G>
+static void l_combo(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  hipLaunchKernelGGL((k_combo<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+template <typename T, int G>
+static void l_proj(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  hipLaunchKernelGGL((k_proj<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+template <typename T, int G>
+static void l_copy(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  hipLaunchKernelGGL((k_copy_scale<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d, src, dst);
+}
+template <typename T, int G>
+static void l_gram(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src) {
+  hipLaunchKernelGGL((k_gram<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d, src);
+}
+
+}  // namespace hl
+
+// Host-visible launch API (ops.h declares these)
+#include "ops.h"
+
+namespace hl {
+
+static bool is64(int prec) { return prec == 0; }
+
+void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT,
+              int wyp) {
+  if (nt <= 0) return;
+  SddmmArgs a{xrole, msel, wT, wyp};
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_sddmm, s, t, nt, d, a);
+  else HL_DISPATCH_G(float, R, l_sddmm, s, t, nt, d, a);
+}
+void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_lrdots, s, t, nt, d, xrole);
+  else HL_DISPATCH_G(float, R, l_lrdots, s, t, nt, d, xrole);
+}
+void op_spmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int zsel,
+             int outrole, int mode) {
+  if (nt <= 0) return;
+  SpmmArgs a{xrole, msel, zsel, outrole};
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_spmm, s, t, nt, d, a, mode);
+  else HL_DISPATCH_G(float, R, l_spmm, s, t, nt, d, a, mode);
+}
+void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_combo, s, t, nt, d);
+  else HL_DISPATCH_G(float, R, l_combo, s, t, nt, d);
+}
+void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_proj, s, t, nt, d);
+  else HL_DISPATCH_G(float, R, l_proj, s, t, nt, d);
+}
+void op_copy_scale(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_copy, s, t, nt, d, src, dst);
+  else HL_DISPATCH_G(float, R, l_copy, s, t, nt, d, src, dst);
+}
+void op_gram(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_gram, s, t, nt, d, src);
+  else HL_DISPATCH_G(float, R, l_gram, s, t, nt, d, src);
+}
+
+template <typename T, int G, typename S>
+static void l_pack(hipStream_t s, const Tile *t, int nt, const InstDev *d, const S *src, int r, int64_t ld, int dst,
+                   double scale) {
+  hipLaunchKernelGGL((k_pack<T, G, S>), dim3(nt), dim3(BLOCK), 0, s, t, d, src, r, ld, dst, scale);
+}
+template <typename T, int G>
+static void l_pack_d(hipStream_t s, const Tile *t, int nt, const InstDev *d, const double *src, int r, int64_t ld,
+                     int dst, double scale) {
+  l_pack<T, G, double>(s, t, nt, d, src, r, ld, dst, scale);
+}
+template <typename T, int G>
+static void l_pack_o(hipStream_t s, const Tile *t, int nt, const InstDev *d, const T *src, int r, int64_t ld, int dst,
+                     double scale) {
+  l_pack<T, G, T>(s, t, nt, d, src, r, ld, dst, scale);
+}
+
+void op_pack_f64(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, const double *src, int r,
+                 int64_t ld, int dst, double scale) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_pack_d, s, t, nt, d, src, r, ld, dst, scale);
+  else HL_DISPATCH_G(float, R, l_pack_d, s, t, nt, d, src, r, ld, dst, scale);
+}
+void op_pack_op(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, const void *src, int r,
+                int64_t ld, int dst) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_pack_o, s, t, nt, d, (const double *)src, r, ld, dst, 1.0);
+  else HL_DISPATCH_G(float, R, l_pack_o, s, t, nt, d, (const float *)src, r, ld, dst, 1.0);
+}
+
+template <typename T, int G, typename S>
+static void l_unpack(hipStream_t s, const Tile *t, int nt, const InstDev *d, S *out, int r, int64_t ld, int src) {
+  hipLaunchKernelGGL((k_unpack<T, G, S>), dim3(nt), dim3(BLOCK), 0, s, t, d, out, r, ld, src);
+}
+template <typename T, int G>
+static void l_unpack_d(hipStream_t s, const Tile *t, int nt, const InstDev *d, double *out, int r, int64_t ld, int src) {
+  l_unpack<T, G, double>(s, t, nt, d, out, r, ld, src);
+}
+template <typename T, int G>
+static void l_unpack_o(hipStream_t s, const Tile *t, int nt, const InstDev *d, T *out, int r, int64_t ld, int src) {
+  l_unpack<T, G, T>(s, t, nt, d, out, r, ld, src);
+}
+void op_unpack_f64(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, double *out, int r,
+                   int64_t ld, int src) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_unpack_d, s, t, nt, d, out, r, ld, src);
+  else HL_DISPATCH_G(float, R, l_unpack_d, s, t, nt, d, out, r, ld, src);
+}
+void op_unpack_op(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, void *out, int r,
+                  int64_t ld, int src) {
+  if (nt <= 0) return;
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_unpack_o, s, t, nt, d, (double *)out, r, ld, src);
+  else HL_DISPATCH_G(float, R, l_unpack_o, s, t, nt, d, (float *)out, r, ld, src);
+}
+
+template <typename T, int GS, int GD>
+static void l_fw2(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  hipLaunchKernelGGL((k_fw_apply<T, GS, GD>), dim3(nt), dim3(BLOCK), 0, s, t, d, src, dst);
+}
+template <typename T, int GS, int GD>
+static void l_rot2(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  hipLaunchKernelGGL((k_rotate<T, GS, GD>), dim3(nt), dim3(BLOCK), 0, s, t, d, src, dst);
+}
+
+template <typename T, int GS>
+static void l_fw_gd(int GD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst, bool rot) {
+  switch (GD) {
+    case 1: rot ? l_rot2<T, GS, 1>(s, t, nt, d, src, dst) : l_fw2<T, GS, 1>(s, t, nt, d, src, dst); break;
+    case 2: rot ? l_rot2<T, GS, 2>(s, t, nt, d, src, dst) : l_fw2<T, GS, 2>(s, t, nt, d, src, dst); break;
+    case 4: rot ? l_rot2<T, GS, 4>(s, t, nt, d, src, dst) : l_fw2<T, GS, 4>(s, t, nt, d, src, dst); break;
+    case 8: rot ? l_rot2<T, GS, 8>(s, t, nt, d, src, dst) : l_fw2<T, GS, 8>(s, t, nt, d, src, dst); break;
+    case 16: rot ? l_rot2<T, GS, 16>(s, t, nt, d, src, dst) : l_fw2<T, GS, 16>(s, t, nt, d, src, dst); break;
+    case 32:
+      if constexpr (sizeof(T) == 8) { rot ? l_rot2<T, GS, 32>(s, t, nt, d, src, dst) : l_fw2<T, GS, 32>(s, t, nt, d, src, dst); }
+      break;
+    default: break;
+  }
+}
+template <typename T>
+static void l_fw_gs(int GS, int GD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst, bool rot) {
+  switch (GS) {
+    case 1: l_fw_gd<T, 1>(GD, s, t, nt, d, src, dst, rot); break;
+    case 2: l_fw_gd<T, 2>(GD, s, t, nt, d, src, dst, rot); break;
+    case 4: l_fw_gd<T, 4>(GD, s, t, nt, d, src, dst, rot); break;
+    case 8: l_fw_gd<T, 8>(GD, s, t, nt, d, src, dst, rot); break;
+    case 16: l_fw_gd<T, 16>(GD, s, t, nt, d, src, dst, rot); break;
+    case 32:
+      if constexpr (sizeof(T) == 8) l_fw_gd<T, 32>(GD, s, t, nt, d, src, dst, rot);
+      break;
+    default: break;
+  }
+}
+void op_fw_apply(int prec, int RS, int RD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  if (nt <= 0) return;
+  if (is64(prec)) l_fw_gs<double>(g_of<double>(RS), g_of<double>(RD), s, t, nt, d, src, dst, false);
+  else l_fw_gs<float>(g_of<float>(RS), g_of<float>(RD), s, t, nt, d, src, dst, false);
+}
+void op_rotate(int prec, int RS, int RD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
+  if (nt <= 0) return;
+  if (is64(prec)) l_fw_gs<double>(g_of<double>(RS), g_of<double>(RD), s, t, nt, d, src, dst, true);
+  else l_fw_gs<float>(g_of<float>(RS), g_of<float>(RD), s, t, nt, d, src, dst, true);
+}
+
+void op_gen_constraints(int prec, hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d, int wT) {
+  if (ni <= 0 || maxm <= 0) return;
+  SddmmArgs a{0, -1, wT, 1};
+  dim3 g((maxm + BLOCK - 1) / BLOCK, ni);
+  if (is64(prec)) hipLaunchKernelGGL(k_gen_constraints<double>, g, dim3(BLOCK), 0, s, ilist, d, a);
+  else hipLaunchKernelGGL(k_gen_constraints<float>, g, dim3(BLOCK), 0, s, ilist, d, a);
+}
+void op_pairvals(int prec, hipStream_t s, const int32_t *ilist, int ni, int maxpairs, const InstDev *d, int msel,
+                 const double *yext, int general) {
+  if (ni <= 0 || maxpairs <= 0) return;
+  dim3 g((maxpairs + BLOCK - 1) / BLOCK, ni);
+  if (general) {
+    if (is64(prec)) hipLaunchKernelGGL(k_gen_pairvals<double>, g, dim3(BLOCK), 0, s, ilist, d, msel, yext ? 1 : 0, yext);
+    else hipLaunchKernelGGL(k_gen_pairvals<float>, g, dim3(BLOCK), 0, s, ilist, d, msel, yext ? 1 : 0, yext);
+  } else {
+    if (is64(prec)) hipLaunchKernelGGL(k_pairvals<double>, g, dim3(BLOCK), 0, s, ilist, d, msel, yext);
+    else hipLaunchKernelGGL(k_pairvals<float>, g, dim3(BLOCK), 0, s, ilist, d, msel, yext);
+  }
+}
+void op_fw_den(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_fw_den, dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+void op_fw_den_gen(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d) {
+  if (ni <= 0 || maxm <= 0) return;
+  hipLaunchKernelGGL(k_fw_den_gen, dim3((maxm + BLOCK - 1) / BLOCK, ni), dim3(BLOCK), 0, s, ilist, d);
+}
+void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d) {
+  if (ni <= 0 || maxm <= 0) return;
+  hipLaunchKernelGGL(k_set_p, dim3((maxm + BLOCK - 1) / BLOCK, ni), dim3(BLOCK), 0, s, ilist, d);
+}
+void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra) {
+  if (ni <= 0) return;
+  RedArgs a{op, zsel, R, extra};
+  hipLaunchKernelGGL(k_reduce, dim3(ni), dim3(BLOCK), 0, s, ilist, d, a);
+}
+void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_start, dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_first, dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+void op_lz_spmv(hipStream_t s, const Tile *t, int nt, const InstDev *d, int from_lzv) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_spmv, dim3(nt), dim3(BLOCK), 0, s, t, d, from_lzv);
+}
+void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_dots, dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int final_pass) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_update, dim3(nt), dim3(BLOCK), 0, s, t, d, final_pass);
+}
+void op_lz_scale(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_scale, dim3(nt), dim3(BLOCK), 0, s, t, d);
+}
+void op_lz_combine(hipStream_t s, const Tile *t, int nt, const InstDev *d, int to_lzv) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_combine, dim3(nt), dim3(BLOCK), 0, s, t, d, to_lzv);
+}
+
+}  // namespace hl

@@ -1,0 +1,48 @@
+// Host-callable launchers of the kernels in kernels.hip.  `prec` is
+// 0 for FP64 and 1 for FP32-mixed; R is the padded column count of the
+// U-like buffers of every instance in the launch.
+#pragma once
+#include "internal.h"
+
+namespace hl {
+
+enum SpmmModeH : int { SPM_PLAIN = 0, SPM_TRIAL = 1, SPM_AIPP = 2 };
+enum RedOpH : int {
+  RDH_COMBO = 0, RDH_SDDMM_XT, RDH_TRIAL_PROJ, RDH_PROJ_DOTS, RDH_SDDMM_YP, RDH_AIPP, RDH_EVAL, RDH_LRONLY,
+  RDH_LZ_START, RDH_LZ_H1, RDH_LZ_H2, RDH_LZ_FINAL, RDH_FW_DEN, RDH_SETP, RDH_NORM, RDH_GEN_EXTRA, RDH_GRAM
+};
+
+void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp);
+void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);
+void op_spmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int zsel,
+             int outrole, int mode);
+void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_copy_scale(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst);
+void op_gram(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src);
+void op_pack_f64(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, const double *src, int r,
+                 int64_t ld, int dst, double scale);
+void op_pack_op(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, const void *src, int r,
+                int64_t ld, int dst);
+void op_unpack_f64(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, double *out, int r,
+                   int64_t ld, int src);
+void op_unpack_op(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, void *out, int r,
+                  int64_t ld, int src);
+void op_fw_apply(int prec, int RS, int RD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst);
+void op_rotate(int prec, int RS, int RD, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst);
+void op_gen_constraints(int prec, hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d, int wT);
+void op_pairvals(int prec, hipStream_t s, const int32_t *ilist, int ni, int maxpairs, const InstDev *d, int msel,
+                 const double *yext, int general);
+void op_fw_den(hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_fw_den_gen(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d);
+void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d);
+void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra);
+void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_lz_spmv(hipStream_t s, const Tile *t, int nt, const InstDev *d, int from_lzv);
+void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int final_pass);
+void op_lz_scale(hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_lz_combine(hipStream_t s, const Tile *t, int nt, const InstDev *d, int to_lzv);
+
+}  // namespace hl

@@ -1,0 +1,75 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/hallar.h declares, validates problem descriptors before touching
+the device, and its default solver constants equal the oracle's readings."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import sdp_instances as si
+from paper_2505_13719_amd import hallar as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hallar.h")).read()
+    return sorted(set(re.findall(r"\b(hallar_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = H.load()
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(H.EXPORTS)
+
+
+def test_default_options_match_oracle_readings():
+    o = H.options()
+    ref = oracle.Options()
+    for k in ("eps", "beta1", "beta_growth", "beta_max", "infeas_ratio", "pinf_gate", "eps1", "eps_floor",
+              "eps_decay", "sigma", "chi", "lam0", "drop_tol", "eig_frac"):
+        assert getattr(o, k) == pytest.approx(getattr(ref, k)), k
+
+
+def _bad(prob, code):
+    with pytest.raises(H.HallarError) as e:
+        H.hallar_footprint(prob)
+    assert e.value.status == code
+
+
+def test_descriptor_validation():
+    p = si.random_hslr(8, 4, 0)
+    # lower-triangle entry
+    q = si.random_hslr(8, 4, 0)
+    q.row, q.col = q.col.copy(), q.row.copy()
+    off = q.row != q.col
+    if off.any():
+        _bad(q, 1)
+    # constraint index beyond m
+    q = si.random_hslr(8, 4, 0)
+    q.con = q.con.copy(); q.con[0] = 99
+    _bad(q, 1)
+    # NaN value
+    q = si.random_hslr(8, 4, 0)
+    q.val = q.val.copy(); q.val[3] = np.nan
+    _bad(q, 9)
+    # low-rank term on a constraint: unsupported in this build
+    q = si.random_hslr(8, 4, 0, lowrank_nonobjective=True)
+    _bad(q, 2)
+    # a valid one has a positive, deterministic footprint
+    b1 = H.hallar_footprint(p)
+    b2 = H.hallar_footprint(p)
+    assert b1 == b2 > 0
+    assert H.hallar_footprint(p, H.FP32_MIXED) < b1
+
+
+def test_footprint_grows_with_size():
+    small = si.maxcut_problem(50, *si.er_edges(50, 0.1, np.random.default_rng(0)))
+    big = si.maxcut_problem(500, *si.er_edges(500, 0.1, np.random.default_rng(0)))
+    assert H.hallar_footprint(big) > H.hallar_footprint(small)
