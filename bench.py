@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X HALLaR hot path: SDP solves/s at 1e-5 relative
+gap on one GPU, with the dominant kernel's achieved HBM bandwidth.
+
+One step is one complete HALLaR solve (operators, ADAP-FISTA/ADAP-AIPP,
+Lanczos, Frank-Wolfe, multiplier updates, relative termination) of a seeded
+synthetic instance resident in HBM.  Workloads (--workload):
+  torus   MaxCut SDP, 1000 x 1000 torus (n = 1e6), +-1 weights, FP32-mixed,
+          rank cap 32 (default)
+  er800   MaxCut SDP, G(800, 0.02), unit weights, FP64, rank cap 16
+  theta   Lovasz theta SDP, G(5e4, avg deg 10), FP32-mixed, rank cap 64
+  mc      matrix completion, 1e5 x 1e5 rank 3, m = 1.2e7, FP32-mixed
+  served  stream of MaxCut requests (n log-uniform in [100, 2e4], deg 8,
+          +-1 weights) through the continuous-batching pool; reports p50/p99
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import sdp_instances as si
+    from paper_2505_13719_amd import hallar as H
+    if name == "torus":
+        return si.maxcut_torus(1000, 1000, seed=2), H.FP32_MIXED, dict(rank_cap=32), \
+            {"workload": "maxcut_torus_1000x1000_pm1", "n": 10 ** 6, "edges": 2 * 10 ** 6, "rank_cap": 32}
+    if name == "er800":
+        return si.maxcut_er_800(1), H.FP64, dict(rank_cap=16), \
+            {"workload": "maxcut_er_800_p0.02", "n": 800, "rank_cap": 16}
+    if name == "theta":
+        return si.theta_er(50_000, 10.0, seed=3), H.FP32_MIXED, dict(rank_cap=64), \
+            {"workload": "theta_er_50000_deg10", "n": 50_000, "rank_cap": 64}
+    if name == "mc":
+        n1 = n2 = 100_000
+        return si.mc_planted(n1, n2, 3, 20 * 3 * (n1 + n2), seed=4), H.FP32_MIXED, dict(rank_cap=16), \
+            {"workload": "matrix_completion_1e5x1e5_r3_m1.2e7", "n": n1 + n2, "m": 20 * 3 * (n1 + n2)}
+    raise ValueError(name)
+
+
+def roofline_from_profile(prof):
+    """Dominant kernel class by time among the memory-streaming classes."""
+    cands = {k: v for k, v in prof.items() if v["bytes"] > 0 and v["ms"] > 0}
+    if not cands:
+        return None, {}
+    dom = max(cands, key=lambda k: cands[k]["ms"])
+    v = cands[dom]
+    achieved = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+    table = {k: dict(ms=round(x["ms"], 3), launches=x["launches"],
+                     gbs=round(x["bytes"] / (x["ms"] * 1e-3) / 1e9, 1) if x["ms"] > 0 and x["bytes"] > 0 else None,
+                     us_per_launch=round(1e3 * x["ms"] / x["launches"], 2) if x["launches"] else None)
+             for k, x in prof.items()}
+    return dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=v["bytes"] / max(v["launches"], 1),
+                us_per_launch=1e3 * v["ms"] / max(v["launches"], 1)), table
+
+
+def cpu_baseline(prob, res, budget_s=20.0):
+    """Oracle timed on a bounded sample: FISTA-trial-equivalent evaluations
+    (2 A~(UU^T) + 1 adjoint) and Lanczos products on the same instance at the
+    GPU solve's final rank, scaled by the GPU solve's operation counts."""
+    import numpy as np
+
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = 1
+    r = max(int(res["rank"]), 1)
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal((prob.n, r)) / math.sqrt(prob.n * r) * math.sqrt(prob.tau2)
+    counters = dict(sddmm=0, spmm=0)
+    g = oracle.ALFunction(prob, np.zeros(prob.m), 1.0, counters)
+    t0 = time.perf_counter()
+    trials = 0
+    while True:
+        gv, T, y = g.eval(U)
+        G = g.grad_from(U, y)
+        g.eval(U - 1e-3 * G)
+        trials += 1
+        if time.perf_counter() - t0 > budget_s / 2 or trials >= 50:
+            break
+    t_trial = (time.perf_counter() - t0) / trials
+    ptil = np.concatenate([[1.0], np.zeros(prob.m)])
+    M = oracle.adjoint_sparse(prob, ptil)
+    t1 = time.perf_counter()
+    kmax = 32 if prob.n > 100_000 else 64
+    lam, v, info = oracle.min_eig(lambda x: M @ x, prob.n, rng.standard_normal(prob.n), tol=1e-30, kmax=kmax,
+                                  max_restarts=1)
+    t_mv = (time.perf_counter() - t1) / max(info["iters"], 1)
+    est = res["n_fista_trials"] * t_trial + res["n_matvec"] * t_mv
+    return dict(value=round(1.0 / est, 8), unit="solves/s", cores=int(cores), kind="oracle",
+                sample=f"{trials} FISTA-trial evaluations (2 SDDMM + 1 SpMM, rank {r}) and {info['iters']} "
+                       f"Lanczos products with full reorthogonalisation on the full instance, "
+                       f"{t_trial:.3f} s/trial and {t_mv * 1e3:.1f} ms/product, scaled by the GPU solve's "
+                       f"{res['n_fista_trials']} trials and {res['n_matvec']} products "
+                       f"(estimated oracle solve {est:.0f} s)",
+                est_seconds=round(est, 1))
+
+
+def bench_solve(args):
+    import numpy as np  # noqa: F401
+    import torch
+
+    import sdp_instances as si
+    from paper_2505_13719_amd import hallar as H
+
+    prob, prec, kw, cfg = workload(args.workload)
+    if args.precision:
+        prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
+    dev = torch.device("cuda:0")
+    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, **kw)
+    t_build = time.perf_counter()
+    h = H.hallar_create(prob, prec, opts)
+    t_build = time.perf_counter() - t_build
+    U0 = torch.tensor(si.gaussian_u0(prob.n, 7), device=dev)
+    res = None
+    for _ in range(args.warmup):
+        res = H.hallar_solve(h, U0)
+        print(f"[bench] warmup solve: {res['status']} {res['seconds']:.2f}s", file=sys.stderr, flush=True)
+    H.hallar_profile(h, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = H.hallar_solve(h, U0)
+        print(f"[bench] step {k}: {res['status']} pval={res['pval']:.9g} gap={res['gap']:.2e} "
+              f"rank={res['rank']} {res['seconds']:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = H.hallar_profile(h)
+    H.hallar_destroy(h)
+    roof, table = roofline_from_profile(prof)
+    out = {
+        "metric": "SDP solves/s at 1e-5 rel gap",
+        "value": round(args.steps / dt, 6),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == H.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": dict(cfg, precision="fp64" if prec == H.FP64 else "fp32_mixed", eps=1e-5),
+        "solve": {k: res[k] for k in ("status", "pval", "dval", "pinf", "gap", "dinf", "rank", "outer_iters",
+                                      "n_fista_trials", "n_matvec", "n_hlr_iters", "n_eig_calls", "n_rounds",
+                                      "n_truncations")},
+        "roofline": roof,
+        "kernels": table,
+        "create_s": round(t_build, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, res, budget_s=args.cpu_budget)
+    return out
+
+
+def bench_served(args):
+    import numpy as np
+    import torch
+
+    import sdp_instances as si
+    from paper_2505_13719_amd import hallar as H
+
+    nreq = args.served_requests
+    sizes = si.served_stream_sizes(4096, seed=5)[:nreq]
+    rng = np.random.default_rng(6)
+    t_gen = time.perf_counter()
+    reqs = [si.served_request(k, int(n), seed=5) for k, n in enumerate(sizes)]
+    U0s = [si.gaussian_u0(int(n), 1000 + k) for k, n in enumerate(sizes)]
+    t_gen = time.perf_counter() - t_gen
+    opts = H.options(eps=1e-5, rank_cap=32, profile=1)
+    rate = args.rate
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq)) if rate > 0 else np.zeros(nreq)
+    pool = H.hallar_pool_create(int(args.budget_gb * (1 << 30)), args.max_active, H.FP32_MIXED, opts)
+    done = {}
+    nxt = 0
+    max_active = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while len(done) < nreq:
+        now = time.perf_counter() - t0
+        while nxt < nreq and arrivals[nxt] <= now:
+            st = H.hallar_pool_admit(pool, reqs[nxt], nxt, U0=U0s[nxt])
+            if st != "ok":
+                break
+            nxt += 1
+        act = H.hallar_pool_step(pool, 1)
+        max_active = max(max_active, act)
+        tnow = time.perf_counter() - t0
+        for t, r in H.hallar_pool_poll(pool):
+            done[t] = (tnow, r)
+        if act == 0 and nxt < nreq and arrivals[nxt] > tnow:
+            time.sleep(min(arrivals[nxt] - tnow, 0.01))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = H.hallar_pool_profile(pool)
+    H.hallar_pool_destroy(pool)
+    lat = np.array([done[k][0] - arrivals[k] for k in range(nreq)])
+    ok = sum(1 for k in range(nreq) if done[k][1]["status"] == "ok")
+    first = float(arrivals.min())
+    last = max(v[0] for v in done.values())
+    roof, table = roofline_from_profile(prof)
+    out = {
+        "metric": "SDP solves/s at 1e-5 rel gap",
+        "value": round(nreq / (last - first), 4),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * dt, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "served_maxcut_stream", "requests": nreq, "rate_per_s": rate,
+                   "n_range": [int(sizes.min()), int(sizes.max())], "budget_gb": args.budget_gb,
+                   "max_active": args.max_active},
+        "served": {"p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+                   "converged": ok, "max_active": max_active, "gen_s": round(t_gen, 1)},
+        "roofline": roof,
+        "kernels": table,
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="torus", choices=["torus", "er800", "theta", "mc", "served"])
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--served-requests", type=int, default=4096)
+    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--max-active", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    out = bench_served(args) if args.workload == "served" else bench_solve(args)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -92,13 +92,14 @@ typedef struct {
   double sigma, chi, lam0;          /* ADAP-AIPP / ADAP-FISTA universal parameters */
   int32_t fista_max_iter, aipp_max_iter, hlr_max_iter, outer_max_iter;
   double eig_tol, eig_frac;         /* Lanczos: residual <= max(eig_frac eps_t / tau^2, eig_tol max(1,|lambda|)) */
-  int32_t eig_kmax;                 /* Lanczos basis size before a thick restart (<= 128) */
+  int32_t eig_kmax;                 /* Lanczos basis size before a thick restart (<= 64) */
   int32_t eig_max_iter;             /* Lanczos matvec cap per eigen solve */
-  int32_t rank_cap;                 /* 0 = none (then at most 64 columns) */
+  int32_t rank_cap;                 /* columns of U after a step; 0 = none (then at most 63) */
   double drop_tol;                  /* drop directions with sigma^2 <= drop_tol sigma_max^2 */
   double time_limit;                /* seconds per solve */
   uint64_t seed;                    /* Lanczos start vectors and default U0 */
   int32_t verbose;
+  int32_t profile;                  /* 1: time every kernel class with HIP events (see hallar_profile) */
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);
@@ -214,6 +215,19 @@ hallar_status hallar_pool_poll(hallar_pool_t pool, int64_t *tickets, hallar_resu
 
 /* Bytes in use / budget of the pool. */
 hallar_status hallar_pool_usage(hallar_pool_t pool, size_t *used, size_t *budget);
+
+/* ---- profiling (opts.profile = 1) ---- */
+/* Kernel classes timed with HIP events recorded on the library's stream
+ * around each launch: 0 SDDMM (A~(UU^T) + AL epilogue), 1 SpMM
+ * ((C + A*(y))U + epilogue), 2 Lanczos SpMV, 3 Lanczos reorthogonalisation,
+ * 4 vector updates, 5 reductions, 6 other.  For each class: total
+ * milliseconds, launches, and algorithmic bytes (every index, value and
+ * constraint array read once, U read once, outputs written once).  Counters
+ * accumulate since the handle/pool was created or last reset (reset != 0).
+ * Arrays are host, length n_classes (<= 7). */
+hallar_status hallar_profile(hallar_t h, double *ms, int64_t *launches, double *bytes, int32_t n_classes, int32_t reset);
+hallar_status hallar_pool_profile(hallar_pool_t pool, double *ms, int64_t *launches, double *bytes, int32_t n_classes,
+                                  int32_t reset);
 
 #ifdef __cplusplus
 }

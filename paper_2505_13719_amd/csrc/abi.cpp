@@ -402,7 +402,7 @@ hallar_status hallar_pool_admit(hallar_pool_t pool, const hallar_problem *prob, 
   }
   S.U0ext = S.dev.lzv;
   S.U0r = 1;
-  S.seed = P.opts.seed + (uint64_t)ticket * 7919ull;
+  S.seed = P.opts.seed;  // same start vectors as a standalone solve of this request
   S.ticket = ticket;
   hl::slot_start_solve(P, s);
   return HALLAR_OK;
@@ -432,6 +432,35 @@ hallar_status hallar_pool_poll(hallar_pool_t pool, int64_t *tickets, hallar_resu
   }
   *n_done = k;
   return HALLAR_OK;
+}
+
+static hallar_status profile_out(hl::Pool &P, double *ms, int64_t *launches, double *bytes, int32_t nc, int32_t reset) {
+  if (nc < 0 || nc > hl::KC_N) return HALLAR_E_INVALID;
+  for (int c = 0; c < nc; ++c) {
+    if (ms) ms[c] = P.prof_ms[c];
+    if (launches) launches[c] = P.prof_n[c];
+    if (bytes) bytes[c] = P.prof_bytes[c];
+  }
+  if (reset)
+    for (int c = 0; c < hl::KC_N; ++c) {
+      P.prof_ms[c] = 0;
+      P.prof_n[c] = 0;
+      P.prof_bytes[c] = 0;
+    }
+  return HALLAR_OK;
+}
+
+hallar_status hallar_profile(hallar_t h, double *ms, int64_t *launches, double *bytes, int32_t n_classes, int32_t reset) {
+  if (!h) return fail(nullptr, HALLAR_E_INVALID, "bad handle");
+  const hallar_status st = profile_out(h->P, ms, launches, bytes, n_classes, reset);
+  return st == HALLAR_OK ? st : fail(h, st, "n_classes out of range");
+}
+
+hallar_status hallar_pool_profile(hallar_pool_t pool, double *ms, int64_t *launches, double *bytes, int32_t n_classes,
+                                  int32_t reset) {
+  if (!pool) return fail(nullptr, HALLAR_E_INVALID, "pool is NULL");
+  const hallar_status st = profile_out(pool->P, ms, launches, bytes, n_classes, reset);
+  return st == HALLAR_OK ? st : failp(pool, st, "n_classes out of range");
 }
 
 hallar_status hallar_pool_usage(hallar_pool_t pool, size_t *used, size_t *budget) {

@@ -194,6 +194,11 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
   HL_TRY(hipHostMalloc((void **)&P.h_up, sizeof(double) * P.up_cap, hipHostMallocDefault), "hipHostMalloc upload");
   HL_TRY(hipMalloc((void **)&P.d_dl, sizeof(double) * P.dl_cap), "hipMalloc download");
   HL_TRY(hipHostMalloc((void **)&P.h_dl, sizeof(double) * P.dl_cap, hipHostMallocDefault), "hipHostMalloc download");
+  P.profile = opts.profile != 0;
+  if (P.profile) {
+    P.events.resize(8192);
+    for (auto &ev : P.events) HL_TRY(hipEventCreate(&ev), "hipEventCreate");
+  }
   if (arena_bytes > 0) {
     if (!P.arena.init(arena_bytes, err)) return HALLAR_E_OOM;
     P.use_arena = true;
@@ -213,6 +218,8 @@ void pool_release(Pool &P) {
   };
   fr(P.d_insts); fr(P.d_prm); fr(P.d_res); fr(P.d_tiles); fr(P.d_ilist); fr(P.d_up); fr(P.d_dl);
   frh(P.h_prm); frh(P.h_res); frh(P.h_tiles); frh(P.h_ilist); frh(P.h_up); frh(P.h_dl);
+  for (auto &ev : P.events) (void)hipEventDestroy(ev);
+  P.events.clear();
   P.d_insts = nullptr;
   P.arena.release();
 }
@@ -400,7 +407,63 @@ struct Group {
   int maxm, maxp;
   const PendingOp *op;
   int first_slot;
+  std::vector<int> slots;
 };
+
+// ------------------------------------------------------------------ profiling
+struct ProfScope {
+  Pool &P;
+  int cls, e0 = -1;
+  double bytes;
+  ProfScope(Pool &p, int c, double b) : P(p), cls(c), bytes(b) {
+    if (P.profile && P.ev_used + 2 <= (int)P.events.size()) {
+      e0 = P.ev_used;
+      P.ev_used += 2;
+      (void)hipEventRecord(P.events[e0], P.stream);
+    }
+  }
+  ~ProfScope() {
+    if (e0 >= 0) {
+      (void)hipEventRecord(P.events[e0 + 1], P.stream);
+      P.recs.push_back(ProfRec{cls, e0, e0 + 1, bytes});
+    }
+  }
+};
+
+static void prof_collect(Pool &P) {
+  for (const ProfRec &r : P.recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P.events[r.e0], P.events[r.e1]) == hipSuccess) {
+      P.prof_ms[r.cls] += ms;
+      P.prof_n[r.cls] += 1;
+      P.prof_bytes[r.cls] += r.bytes;
+    }
+  }
+  P.recs.clear();
+  P.ev_used = 0;
+}
+
+// algorithmic bytes of one launch over the instances of a group
+struct GroupBytes {
+  double sddmm = 0, spmm_core = 0, urow = 0, lz_spmv = 0, vec_n8 = 0;
+};
+
+static void launch_group(Pool &P, const Group &g);
+
+static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int R) {
+  GroupBytes b;
+  const double sz = P.prec == 0 ? 8.0 : 4.0;
+  for (int s : slots) {
+    const HostProblem &h = P.slots[s]->hp;
+    const double n = h.n, Pp = (double)h.npairs, nl = (double)h.nlower, m = h.m;
+    b.urow += n * R * sz;
+    b.sddmm += n * R * sz + (n + 1) * 4 + Pp * (4 + (h.direct ? 4 + sz : 0) + (h.has_c ? sz : 0)) + 16 * m;
+    b.spmm_core += n * R * sz + 2 * (n + 1) * 4 + Pp * (4 + sz) + nl * 8;
+    b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 8 + 2 * (n + 1) * 4;
+    b.vec_n8 += n * 8;
+  }
+  return b;
+}
 
 static void launch_group(Pool &P, const Group &g) {
   hipStream_t st = P.stream;
@@ -416,85 +479,152 @@ static void launch_group(Pool &P, const Group &g) {
   const int prec = P.prec;
   const int R = g.R;
   const PendingOp &o = *g.op;
-  auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
-    op_lr_dots(prec, R, st, T, nt, D, xrole);
-    op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
-    if (gni > 0) {
-      op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
-      if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
+  const GroupBytes B = P.profile ? group_bytes(P, g.slots, R) : GroupBytes{};
+  const double sz = prec == 0 ? 8.0 : 4.0;
+  double msum = 0, psum = 0;
+  if (P.profile)
+    for (int s : g.slots) {
+      msum += P.slots[s]->hp.m;
+      psum += (double)P.slots[s]->hp.npairs;
     }
-    op_reduce(st, IL, ni, D, red_op, zsel, R, 0);
+  auto red = [&](int op, int zsel) {
+    ProfScope ps(P, KC_REDUCE, 0.0);
+    op_reduce(st, IL, ni, D, op, zsel, R, 0);
+  };
+  auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
+    {
+      ProfScope ps(P, KC_SDDMM, B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0));
+      op_lr_dots(prec, R, st, T, nt, D, xrole);
+      op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
+      if (gni > 0) {
+        op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
+        if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
+      }
+    }
+    red(red_op, zsel);
   };
   switch (g.code) {
     case OP_TRIAL:
-      op_combo(prec, R, st, T, nt, D);
-      op_reduce(st, IL, ni, D, RDH_COMBO, 0, R, 0);
+      {
+        ProfScope ps(P, KC_VEC, 4 * B.urow);
+        op_combo(prec, R, st, T, nt, D);
+      }
+      red(RDH_COMBO, 0);
       sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
-      op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
-      op_reduce(st, IL, ni, D, RDH_TRIAL_PROJ, 0, R, 0);
-      op_proj(prec, R, st, T, nt, D);
-      op_reduce(st, IL, ni, D, RDH_PROJ_DOTS, 0, R, 0);
+      {
+        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow);
+        op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
+      }
+      red(RDH_TRIAL_PROJ, 0);
+      {
+        ProfScope ps(P, KC_VEC, 5 * B.urow);
+        op_proj(prec, R, st, T, nt, D);
+      }
+      red(RDH_PROJ_DOTS, 0);
       sddmm(RZ, 1, 0, 0, RDH_SDDMM_YP, 1);
       break;
     case OP_GRAD:
-      op_spmm(prec, R, st, T, nt, D, RZ, 1, 1, 0, SPM_AIPP);
-      op_reduce(st, IL, ni, D, RDH_AIPP, 0, R, 0);
+      {
+        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow);
+        op_spmm(prec, R, st, T, nt, D, RZ, 1, 1, 0, SPM_AIPP);
+      }
+      red(RDH_AIPP, 0);
       break;
     case OP_EVAL:
       sddmm(o.xrole, o.msel, o.wT, o.wyp, RDH_EVAL, o.zsel);
       break;
     case OP_COPY:
-      op_copy_scale(prec, R, st, T, nt, D, o.src, o.dst);
-      op_reduce(st, IL, ni, D, RDH_NORM, 0, R, 0);
+      {
+        ProfScope ps(P, KC_VEC, 2 * B.urow);
+        op_copy_scale(prec, R, st, T, nt, D, o.src, o.dst);
+      }
+      red(RDH_NORM, 0);
       break;
     case OP_PACK:
-      op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
-      op_reduce(st, IL, ni, D, RDH_NORM, 0, R, 0);
+      {
+        ProfScope ps(P, KC_OTHER, 0.0);
+        op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
+      }
+      red(RDH_NORM, 0);
       break;
     case OP_LZ_BEGIN:
-      if (dni > 0) op_pairvals(prec, st, DL, dni, g.maxp, D, 2, nullptr, 0);
-      if (gni > 0) op_pairvals(prec, st, GL, gni, g.maxp, D, 2, nullptr, 1);
-      op_lz_start(st, T, nt, D);
-      op_reduce(st, IL, ni, D, RDH_LZ_START, 0, R, 0);
-      op_lz_first(st, T, nt, D);
+      {
+        ProfScope ps(P, KC_OTHER, 0.0);
+        if (dni > 0) op_pairvals(prec, st, DL, dni, g.maxp, D, 2, nullptr, 0);
+        if (gni > 0) op_pairvals(prec, st, GL, gni, g.maxp, D, 2, nullptr, 1);
+        op_lz_start(st, T, nt, D);
+      }
+      red(RDH_LZ_START, 0);
+      {
+        ProfScope ps(P, KC_LZ_ORTH, 2 * B.vec_n8);
+        op_lz_first(st, T, nt, D);
+      }
       break;
     case OP_LZ_STEPS:
       for (int k = 0; k < o.steps; ++k) {
-        op_lz_spmv(st, T, nt, D, 0);
-        op_lz_dots(st, T, nt, D);
-        op_reduce(st, IL, ni, D, RDH_LZ_H1, 0, R, 0);
-        op_lz_update(st, T, nt, D, 0);
-        op_lz_dots(st, T, nt, D);
-        op_reduce(st, IL, ni, D, RDH_LZ_H2, 0, R, 0);
-        op_lz_update(st, T, nt, D, 1);
-        op_reduce(st, IL, ni, D, RDH_LZ_FINAL, 0, R, 0);
-        op_lz_scale(st, T, nt, D);
+        double vb = 0;  // basis bytes of this step's two dots + two updates
+        if (P.profile)
+          for (int s : g.slots) {
+            const Slot &S = *P.slots[s];
+            if (k < S.prm.lz_steps) vb += 4.0 * (S.prm.lz_j + k + 1) * S.hp.n * 8 + 8.0 * S.hp.n * 8;
+          }
+        {
+          ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv);
+          op_lz_spmv(st, T, nt, D, 0);
+        }
+        {
+          ProfScope ps(P, KC_LZ_ORTH, vb);
+          op_lz_dots(st, T, nt, D);
+          op_reduce(st, IL, ni, D, RDH_LZ_H1, 0, R, 0);
+          op_lz_update(st, T, nt, D, 0);
+          op_lz_dots(st, T, nt, D);
+          op_reduce(st, IL, ni, D, RDH_LZ_H2, 0, R, 0);
+          op_lz_update(st, T, nt, D, 1);
+          op_reduce(st, IL, ni, D, RDH_LZ_FINAL, 0, R, 0);
+          op_lz_scale(st, T, nt, D);
+        }
       }
       break;
     case OP_LZ_RITZ:
-      op_lz_combine(st, T, nt, D, 1);
-      break;
     case OP_LZ_RESTART:
-      op_lz_combine(st, T, nt, D, 0);
+      {
+        ProfScope ps(P, KC_LZ_ORTH, 0.0);
+        op_lz_combine(st, T, nt, D, g.code == OP_LZ_RITZ ? 1 : 0);
+      }
       break;
     case OP_FW_PREP:
-      op_fw_den(st, T, nt, D);
-      if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
-      op_reduce(st, IL, ni, D, RDH_FW_DEN, 0, R, 0);
+      {
+        ProfScope ps(P, KC_OTHER, 0.0);
+        op_fw_den(st, T, nt, D);
+        if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
+      }
+      red(RDH_FW_DEN, 0);
       break;
     case OP_FW_APPLY:
-      op_fw_apply(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      {
+        ProfScope ps(P, KC_VEC, 0.0);
+        op_fw_apply(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      }
       break;
     case OP_SETP:
-      op_set_p(st, IL, ni, g.maxm, D);
-      op_reduce(st, IL, ni, D, RDH_SETP, 0, R, 0);
+      {
+        ProfScope ps(P, KC_VEC, 0.0);
+        op_set_p(st, IL, ni, g.maxm, D);
+      }
+      red(RDH_SETP, 0);
       break;
     case OP_GRAM:
-      op_gram(prec, R, st, T, nt, D, o.src);
-      op_reduce(st, IL, ni, D, RDH_GRAM, 0, R, 0);
+      {
+        ProfScope ps(P, KC_OTHER, 0.0);
+        op_gram(prec, R, st, T, nt, D, o.src);
+      }
+      red(RDH_GRAM, 0);
       break;
     case OP_ROTATE:
-      op_rotate(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      {
+        ProfScope ps(P, KC_VEC, 0.0);
+        op_rotate(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
+      }
       break;
     default:
       break;
@@ -559,6 +689,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     for (size_t u = q; u < e; ++u) {
       const int s = run[u];
       Slot &S = *P.slots[s];
+      g.slots.push_back(s);
       for (const Tile &t : S.hp.tiles) P.h_tiles[tpos++] = t;
       P.h_ilist[ipos++] = s;
       g.maxm = std::max(g.maxm, S.hp.m);
@@ -606,6 +737,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   HL_TRY(hipMemcpyAsync(P.h_res, P.d_res, sizeof(InstRes) * maxs, hipMemcpyDeviceToHost, st), "download results");
   if (dl_used) HL_TRY(hipMemcpyAsync(P.h_dl, P.d_dl, sizeof(double) * dl_used, hipMemcpyDeviceToHost, st), "download");
   HL_TRY(hipStreamSynchronize(st), "round");
+  if (P.profile) prof_collect(P);
   P.rounds++;
   did_work = true;
   for (int s : run) {

@@ -26,6 +26,14 @@ class Arena {
   std::map<size_t, size_t> free_;  // offset -> size
 };
 
+// kernel classes of the profile
+enum KClass : int { KC_SDDMM = 0, KC_SPMM, KC_LZ_SPMV, KC_LZ_ORTH, KC_VEC, KC_REDUCE, KC_OTHER, KC_N };
+
+struct ProfRec {
+  int cls, e0, e1;
+  double bytes;
+};
+
 struct Pool {
   int prec = 0;
   hallar_options opts{};
@@ -53,6 +61,13 @@ struct Pool {
   int64_t rounds = 0;
   std::string err;
   hallar_status fatal = HALLAR_OK;
+  // profiling (opts.profile)
+  bool profile = false;
+  std::vector<hipEvent_t> events;
+  int ev_used = 0;
+  std::vector<ProfRec> recs;
+  double prof_ms[KC_N] = {0}, prof_bytes[KC_N] = {0};
+  int64_t prof_n[KC_N] = {0};
 };
 
 // lifetime

@@ -40,7 +40,7 @@ class hallar_options(C.Structure):
                 ("hlr_max_iter", C.c_int32), ("outer_max_iter", C.c_int32), ("eig_tol", C.c_double),
                 ("eig_frac", C.c_double), ("eig_kmax", C.c_int32), ("eig_max_iter", C.c_int32),
                 ("rank_cap", C.c_int32), ("drop_tol", C.c_double), ("time_limit", C.c_double),
-                ("seed", C.c_uint64), ("verbose", C.c_int32)]
+                ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32)]
 
 
 class hallar_result(C.Structure):
@@ -64,7 +64,8 @@ class hallar_eig_info(C.Structure):
 EXPORTS = ["hallar_default_options", "hallar_create", "hallar_destroy", "hallar_last_error", "hallar_describe",
            "hallar_eval_AUUt", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
            "hallar_solve_batch", "hallar_footprint", "hallar_pool_create", "hallar_pool_destroy",
-           "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage"]
+           "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage", "hallar_profile",
+           "hallar_pool_profile"]
 
 _lib = None
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.hallar_pool_step.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
     L.hallar_pool_poll.argtypes = [vp, i64p, C.POINTER(hallar_result), C.c_int32, C.POINTER(C.c_int32)]
     L.hallar_pool_usage.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    L.hallar_profile.argtypes = [vp, f64p, i64p, f64p, C.c_int32, C.c_int32]
+    L.hallar_pool_profile.argtypes = [vp, f64p, i64p, f64p, C.c_int32, C.c_int32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("hallar_default_options", "hallar_last_error"):
@@ -355,3 +358,22 @@ def hallar_pool_usage(pool):
     u, b = C.c_size_t(), C.c_size_t()
     _check(load().hallar_pool_usage(pool, C.byref(u), C.byref(b)))
     return u.value, b.value
+
+
+KERNEL_CLASSES = ["sddmm", "spmm", "lanczos_spmv", "lanczos_reorth", "vector", "reduce", "other"]
+
+
+def _profile(fn, obj, reset):
+    n = len(KERNEL_CLASSES)
+    ms, nl, by = (C.c_double * n)(), (C.c_int64 * n)(), (C.c_double * n)()
+    _check(fn(obj, ms, nl, by, n, 1 if reset else 0))
+    return {k: dict(ms=ms[i], launches=nl[i], bytes=by[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def hallar_profile(h, reset=False):
+    """Per kernel class: total ms, launches, algorithmic bytes (opts.profile = 1)."""
+    return _profile(load().hallar_profile, h, reset)
+
+
+def hallar_pool_profile(pool, reset=False):
+    return _profile(load().hallar_pool_profile, pool, reset)

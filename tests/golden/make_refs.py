@@ -1,0 +1,43 @@
+"""Write tests/golden/refs.json: FP64 oracle solves (eps = 1e-7) of the
+seeded workloads the GPU solve tests compare against.  Calls only oracle/
+and the instance generators."""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import sdp_instances as si  # noqa: E402
+
+
+def cases():
+    yield "maxcut_er800_s1", si.maxcut_er_800(1), dict(rank_cap=16)
+    rng = np.random.default_rng(11)
+    i, j = si.er_edges(400, 0.02, rng)
+    yield "maxcut_pm1_er400", si.maxcut_problem(400, i, j, si.pm1_weights(i.size, rng), name="maxcut_pm1_er400"), {}
+    yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}
+    rng = np.random.default_rng(12)
+    i, j = si.er_edges(300, 0.03, rng)
+    yield "theta_er300", si.theta_problem(300, i, j), {}
+    yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}
+
+
+def main():
+    out = {}
+    for name, prob, kw in cases():
+        t = time.time()
+        r = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=1e-7, time_limit=1800, **kw))
+        out[name] = dict(pval=r.pval, dval=r.dval, status=r.status, rank=r.rank, eps=1e-7, opts=kw,
+                         seconds=round(time.time() - t, 1))
+        print(name, out[name], flush=True)
+    with open(os.path.join(os.path.dirname(__file__), "refs.json"), "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

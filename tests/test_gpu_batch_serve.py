@@ -1,0 +1,99 @@
+"""Batched solves and the serving pool.
+
+* hallar_solve_batch runs uneven instances through shared segment-indexed
+  launches; every result equals the same instance solved alone, bit for
+  bit (fixed-order per-instance reductions, instance-only tile schedules).
+* The pool admits by HBM footprint (E_OOM when a request does not fit),
+  continues batching as arrivals come in, and each served result equals the
+  result of the same request alone.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import sdp_instances as si
+from gpu_util import dev, torch
+from paper_2505_13719_amd import hallar as H
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("status", "pval", "dval", "pinf", "gap", "dinf", "rank", "outer_iters", "n_fista_trials")
+
+
+def _probs():
+    rng = np.random.default_rng(5)
+    out = [si.maxcut_problem(5, *si.cycle_edges(5)), si.theta_problem(10, *si.petersen_edges())]
+    for n in (37, 150, 420, 1100):
+        i, j = si.er_edges(n, 8.0 / (n - 1), rng)
+        out.append(si.maxcut_problem(n, i, j, si.pm1_weights(i.size, rng)))
+    return out
+
+
+def _alone(prob, prec, seed=3):
+    d = dev()
+    h = H.hallar_create(prob, prec, H.options(eps=1e-5))
+    try:
+        return H.hallar_solve(h, torch.tensor(si.gaussian_u0(prob.n, seed), device=d))
+    finally:
+        H.hallar_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
+def test_batch_equals_alone(prec):
+    d = dev()
+    probs = _probs()
+    alone = [_alone(p, prec) for p in probs]
+    hs = [H.hallar_create(p, prec, H.options(eps=1e-5)) for p in probs]
+    try:
+        U0s = [torch.tensor(si.gaussian_u0(p.n, 3), device=d) for p in probs]
+        batch = H.hallar_solve_batch(hs, U0s)
+    finally:
+        for h in hs:
+            H.hallar_destroy(h)
+    for a, b in zip(alone, batch):
+        assert a["status"] == "ok"
+        for k in KEYS:
+            assert a[k] == b[k], (k, a[k], b[k])
+    assert abs(batch[0]["pval"] + 2.5 * (1 + math.cos(math.pi / 5))) <= 1e-5 * 5
+    assert abs(batch[1]["pval"] + 4.0) <= 1e-5 * 5
+
+
+def test_pool_admission_and_mix():
+    probs = _probs()
+    prec = H.FP32_MIXED
+    opts = H.options(eps=1e-5)
+    foot = [H.hallar_footprint(p, prec, opts) for p in probs]
+    # a budget that fits the two largest requests at most
+    budget = sorted(foot)[-1] + sorted(foot)[-2] + (1 << 20)
+    pool = H.hallar_pool_create(budget, 8, prec, opts)
+    try:
+        # a request larger than the whole budget is refused
+        big = si.maxcut_problem(4000, *si.er_edges(4000, 0.01, np.random.default_rng(0)))
+        assert H.hallar_pool_admit(pool, big, 999) == "oom"
+        pending = list(range(len(probs)))
+        done = {}
+        admitted_together = 0
+        steps = 0
+        while pending or len(done) < len(probs):
+            still = []
+            for k in pending:
+                st = H.hallar_pool_admit(pool, probs[k], k, U0=si.gaussian_u0(probs[k].n, 3))
+                if st != "ok":
+                    still.append(k)
+            pending = still
+            used, cap = H.hallar_pool_usage(pool)
+            assert used <= cap
+            active = H.hallar_pool_step(pool, 4)
+            admitted_together = max(admitted_together, active)
+            for t, r in H.hallar_pool_poll(pool):
+                done[t] = r
+            steps += 1
+            assert steps < 100000
+        assert admitted_together >= 2                      # requests overlapped on the device
+    finally:
+        H.hallar_pool_destroy(pool)
+    for k, p in enumerate(probs):
+        a = _alone(p, prec)
+        for key in KEYS:
+            assert a[key] == done[k][key], (k, key, a[key], done[k][key])
