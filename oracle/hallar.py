@@ -16,10 +16,15 @@ defined on its own side):
     ||A(X_t) - b|| > 0.5 ||A(X_{t-1}) - b|| and the relative infeasibility is
     at least 0.1 times the larger of the relative gap and dual infeasibility;
     otherwise beta is kept.
-  * eps_t = max(eps1 * 0.5^(t-1), eps_floor) * (1 + |pval_{t-1}|) with
-    eps1 = 1e-2, eps_floor = 0.2 * eps; the stationarity tolerance handed
+  * eps_t = max(eps1 * 0.5^(t-1), eps_floor) * (1 + max(|pval_{t-1}|, |g_t(U_{t-1})|))
+    with eps1 = 1e-2, eps_floor = 0.2 * eps (pval_0 = C . U_0 U_0^T; the AL
+    value at the start of the outer iteration keeps the scale right when the
+    random start has a tiny objective); the stationarity tolerance handed
     to ADAP-AIPP is rho_t = eps_t (the tolerance Alg. 1 passes to its
-    nonconvex solver).
+    nonconvex solver) divided by tau: G . YY^T = <grad g(Y), Y>/2 moves by up
+    to tau ||R|| / 2 when the stationarity residual is R, so rho_t = eps_t / tau
+    makes the two tolerances commensurate (the paper's Alg. 1 hands eps_t to
+    both; tau = 1 for theta, where the readings coincide).
   * sigma = 0.3, chi = 1e-3, lambda_0 = 10 for the first call, later calls
     start from the last accepted prox stepsize; M_j = max(1, Mbar_{j-1}/2).
     The descent check (eq. subdiff ineq check) allows a slack of
@@ -62,7 +67,7 @@ class Options:
     infeas_ratio: float = 0.5
     pinf_gate: float = 0.1
     balance: float = 3.0
-    rho_over_tau: bool = False
+    rho_over_tau: bool = True
     beta_min: float = 1e-3
     eps1: float = 1e-2
     eps_floor: float = 0.2          # times eps
@@ -73,7 +78,7 @@ class Options:
     lam_grow: float = 1.0
     fista_max_iter: int = 2000
     aipp_max_iter: int = 500
-    hlr_max_iter: int = 200
+    hlr_max_iter: int = 1000
     outer_max_iter: int = 300
     eig_tol: float = 1e-13
     eig_frac: float = 0.1
@@ -284,11 +289,12 @@ def hallar(prob, U0, opts: Options = None, p0=None):
     theta = 0.0
     pval = dval = pinf = gap = dinf = float("nan")
     for t in range(1, opts.outer_max_iter + 1):
-        eps_t = max(opts.eps1 * opts.eps_decay ** (t - 1), opts.eps_floor * opts.eps) * (1.0 + abs(pval_prev))
-        rho = eps_t / (max(1.0, tau) if opts.rho_over_tau else 1.0)
         g = ALFunction(prob, p, beta, counters)
         Yt = U
         gY, _, _ = g.eval(Yt)
+        scale = 1.0 + max(abs(pval_prev), abs(gY))
+        eps_t = max(opts.eps1 * opts.eps_decay ** (t - 1), opts.eps_floor * opts.eps) * scale
+        rho = eps_t / (max(1.0, tau) if opts.rho_over_tau else 1.0)
         hlr_ok = False
         for _ in range(opts.hlr_max_iter):
             counters["hlr_iters"] += 1

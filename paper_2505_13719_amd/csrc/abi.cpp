@@ -74,7 +74,7 @@ void hallar_default_options(hallar_options *o) {
   o->lam0 = 10.0;
   o->fista_max_iter = 2000;
   o->aipp_max_iter = 500;
-  o->hlr_max_iter = 200;
+  o->hlr_max_iter = 1000;
   o->outer_max_iter = 300;
   o->eig_tol = 1e-13;
   o->eig_frac = 0.1;

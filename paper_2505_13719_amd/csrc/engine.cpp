@@ -109,6 +109,10 @@ struct Layout {
   size_t total;
 };
 
+static size_t prows_for(const HostProblem &hp) {
+  return hp.tiles.size() + ((size_t)hp.m + BLOCK - 1) / BLOCK + 1;
+}
+
 static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   Layout L{};
   Carve c;
@@ -153,7 +157,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.hcoef = c.take((KMAX + 1) * 8);
   L.Z0 = c.take(2 * LR_MAX * R_MAX * 8);
   const size_t nt = hp.tiles.size();
-  L.part = c.take((nt + (m + BLOCK - 1) / BLOCK + 1) * PSTRIDE * 8);
+  L.part = c.take(prows_for(hp) * PSTRIDE * 8);
   L.gram = c.take(nt * (size_t)Rcap * Rcap * 8);
   L.tiles = c.take(nt * sizeof(Tile));
   L.ilist = c.take(sizeof(int32_t));
@@ -316,6 +320,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.r0 = h.r0;
   D.direct = h.direct ? 1 : 0;
   D.ntiles = (int32_t)h.tiles.size();
+  D.prows = (int32_t)prows_for(h);
   auto at = [&](size_t off) { return (void *)(base + off); };
   D.rowptr_u = (const int32_t *)at(L.rowptr_u);
   D.col_u = (const int32_t *)at(L.col_u);
@@ -407,6 +412,7 @@ struct Group {
   int maxm, maxp;
   const PendingOp *op;
   int first_slot;
+  int steps;               // Lanczos steps: the largest request of the group
   std::vector<int> slots;
 };
 
@@ -561,7 +567,8 @@ static void launch_group(Pool &P, const Group &g) {
       }
       break;
     case OP_LZ_STEPS:
-      for (int k = 0; k < o.steps; ++k) {
+      // instances with fewer steps skip the extra ones (their lz_steps counter reaches 0)
+      for (int k = 0; k < g.steps; ++k) {
         double vb = 0;  // basis bytes of this step's two dots + two updates
         if (P.profile)
           for (int s : g.slots) {
@@ -690,6 +697,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
       const int s = run[u];
       Slot &S = *P.slots[s];
       g.slots.push_back(s);
+      g.steps = std::max(g.steps, S.op.steps);
       for (const Tile &t : S.hp.tiles) P.h_tiles[tpos++] = t;
       P.h_ilist[ipos++] = s;
       g.maxm = std::max(g.maxm, S.hp.m);
@@ -1061,8 +1069,11 @@ static Task compress(Ctx c, int &buf, int &r, int keep_max, bool &truncated) {
   sym_eig(r, G.data(), w.data(), Q.data());
   const double wmax = std::max(w[r - 1], 0.0);
   std::vector<int> keep;
+  // directions below the storage precision's noise floor are not resolved in
+  // FP32 (sigma ~ 1e-7 sigma_max): drop below max(drop_tol, 1e-10) there
+  const double dtol = c.P.prec == 0 ? c.o.drop_tol : std::max(c.o.drop_tol, 1e-10);
   for (int a = r - 1; a >= 0; --a)
-    if (w[a] > c.o.drop_tol * wmax) keep.push_back(a);
+    if (w[a] > dtol * wmax) keep.push_back(a);
   if (keep.empty()) keep.push_back(r - 1);
   if (keep_max > 0 && (int)keep.size() > keep_max) {
     keep.resize(keep_max);
@@ -1147,11 +1158,14 @@ static Task solve_main(Ctx c) {
   bool have_v = false;
   int t = 0;
   for (t = 1; t <= o.outer_max_iter; ++t) {
-    const double eps_t = std::max(o.eps1 * std::pow(o.eps_decay, t - 1), o.eps_floor * o.eps) * (1.0 + std::fabs(pval_prev));
-    const double rho = eps_t;
     eval(U, 0, 0);
     co_await OpAwait{S};
     double gY = c.res(S_G_EVAL);
+    const double scale = 1.0 + std::max(std::fabs(pval_prev), std::fabs(gY));
+    const double eps_t = std::max(o.eps1 * std::pow(o.eps_decay, t - 1), o.eps_floor * o.eps) * scale;
+    // stationarity tolerance of ADAP-AIPP: G . YY^T = <grad g(Y), Y>/2 moves by
+    // up to tau ||R|| / 2, so rho = eps_t / tau keeps it commensurate with the gap
+    const double rho = eps_t / std::max(1.0, tau);
     bool hlr_ok = false;
     int Y = -1;
     double TYT0 = 0, lmin = 0, eres = 0;
@@ -1162,6 +1176,8 @@ static Task solve_main(Ctx c) {
       U = -1;
       Y = ao.W;
       lam = ao.lam;
+      if (ao.status != 0 && o.verbose >= 2)
+        fprintf(stderr, "[hallar]   aipp failed t=%d it=%d status=%d lam=%.3g rank=%d rho=%.3e\n", t, it, ao.status, ao.lam, r, rho);
       if (ao.status != 0) {
         res.status = ao.status == 2 ? HALLAR_E_NUMERICAL : HALLAR_E_ITER_LIMIT;
         break;
@@ -1183,6 +1199,9 @@ static Task solve_main(Ctx c) {
       eres = eo.res;
       theta = std::max(-lmin, 0.0);
       const double gap = GYY + tau2 * theta;
+      if (o.verbose >= 2)
+        fprintf(stderr, "[hallar]   hlr t=%d it=%d rank=%d lam=%.3g aipp_g=%.10g gap=%.3e eps_t=%.3e theta=%.3e eig_it=%d res=%.2e trials=%lld\n",
+                t, it, r, lam, ao.g, gap, eps_t, theta, eo.iters, eo.res, (long long)res.n_fista_trials);
       if (!finite(gap)) {
         res.status = HALLAR_E_NUMERICAL;
         break;

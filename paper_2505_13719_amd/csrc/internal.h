@@ -15,6 +15,7 @@
 namespace hl {
 
 constexpr int BLOCK = 256;       // threads per workgroup (4 wave64)
+constexpr int RBLOCK = 1024;     // threads of a reduce workgroup (16 wave64)
 constexpr int LR_MAX = 2;        // rank of the low-rank objective term
 constexpr int R_MAX = 64;        // columns of U
 constexpr int KMAX = 64;         // Lanczos basis vectors before a restart
@@ -83,7 +84,8 @@ struct InstDev {
   int32_t n, m, npairs, nlower;
   int32_t r0;           // rank of the low-rank objective term (0: none)
   int32_t direct;       // every constraint has exactly one pair entry and every pair at most one constraint
-  int32_t ntiles, pad_;
+  int32_t ntiles;
+  int32_t prows;        // rows of the partial-sum matrix (slot q of row t at part[q * prows + t])
   // structure (device)
   const int32_t *rowptr_u, *col_u, *pcon;   // upper CSR over S (pair k = position), constraint of pair (0 = none)
   const int32_t *rowptr_l, *col_l, *pid_l;  // strictly-lower transpose of S with pair ids
@@ -108,8 +110,8 @@ struct InstDev {
   double *Z0;                               // 2 x LR_MAX x R_MAX low-rank products D0 K0^T X
   const double *up_base;                    // pool upload buffer (Ritz / restart coefficients, rotations)
   double *dl_base;                          // pool download buffer (Lanczos columns, Gram matrices)
-  double *part;                             // ntiles x PSTRIDE partial sums
-  double *gram;                             // ntiles x R_MAX x R_MAX (compression)
+  double *part;                             // PSTRIDE x prows partial sums, slot-major
+  double *gram;                             // (R x R) x ntiles Gram partials, entry-major
   InstParams *prm;
   InstRes *res;
 };

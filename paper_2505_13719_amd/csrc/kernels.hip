@@ -47,9 +47,10 @@ __device__ __forceinline__ T group_sum(T v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
-// Block reduction of NQ doubles per thread into the tile's partial slots.
+// Block reduction of NQ doubles per thread into partial row `row` of the
+// instance (slot q at part[q * prows + row]).
 template <int NQ>
-__device__ __forceinline__ void block_partials(double (&acc)[NQ], double *dst) {
+__device__ __forceinline__ void block_partials(double (&acc)[NQ], const InstDev &I, int row) {
   __shared__ double red[BLOCK / 64][NQ > 0 ? NQ : 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -62,22 +63,7 @@ __device__ __forceinline__ void block_partials(double (&acc)[NQ], double *dst) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
-    dst[threadIdx.x] = s;
-  }
-}
-
-// Runtime-count variant (count <= PSTRIDE), one value per thread-slot array.
-__device__ __forceinline__ void block_partials_rt(double *acc, int nq, double *dst, double *lds) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int q = 0; q < nq; ++q) {
-    double s = wave_sum(acc[q]);
-    if (lane == 0) lds[wave * PSTRIDE + q] = s;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nq; q += BLOCK) {
-    double s = 0.0;
-    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * PSTRIDE + q];
-    dst[q] = s;
+    I.part[(size_t)threadIdx.x * I.prows + row] = s;
   }
 }
 
@@ -133,12 +119,14 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
     for (int k = k0 + strm; k < k1; k += (1 << plog)) {
       const int j = I.col_u[k];
       const Chunk<T> uj = ldc(X + (size_t)j * R + ch * NC);
-      T d = T(0);
+      // products accumulate in FP64 (also for FP32 U): the AL value that the
+      // FISTA / AIPP tests compare must be exact for the stored iterate
+      double d = 0.0;
 #pragma unroll
-      for (int e = 0; e < NC; ++e) d += ui.v[e] * uj.v[e];
+      for (int e = 0; e < NC; ++e) d += (double)ui.v[e] * (double)uj.v[e];
       d = group_sum<G>(d);
       if (ch == 0) {
-        const double B = (double)d;
+        const double B = d;
         const double w2 = (i == j) ? 1.0 : 2.0;
         const double cv = cu ? (double)cu[k] : 0.0;
         acc[0] += w2 * cv * B;
@@ -165,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
       }
     }
   }
-  block_partials<NQ>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<NQ>(acc, I, tl.lt);
 }
 
 // K^T X for the low-rank objective term (Algorithm 3: Y_0 = K_0^T U), written
@@ -182,6 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_lr_dots(const Tile *__restrict__ tile
   const T *__restrict__ X = role_ptr<T>(I, P, xrole);
   const T *__restrict__ K0 = reinterpret_cast<const T *>(I.K0);
   const int r0 = I.r0;
+  if (r0 == 0) return;  // no low-rank term: nothing to read (uniform per block)
   // thread -> (row offset, chunk); each thread accumulates LR_MAX x NC values
   double acc[LR_MAX * NC];
 #pragma unroll
@@ -213,11 +202,10 @@ __global__ __launch_bounds__(BLOCK) void k_lr_dots(const Tile *__restrict__ tile
     }
   }
   __syncthreads();
-  double *dst = I.part + (size_t)tl.lt * PSTRIDE;
   for (int q = threadIdx.x; q < r0 * R; q += BLOCK) {
     double s = 0.0;
     for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * PSTRIDE + q];
-    dst[4 + q] = s;
+    I.part[(size_t)(4 + q) * I.prows + tl.lt] = s;
   }
 }
 
@@ -247,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_constraints(const int32_t *__rest
     if (a.write_T) I.TY[l] = t;
     I.yp[l] = y;
   }
-  if (blockIdx.x * BLOCK < I.m) block_partials<3>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+  if (blockIdx.x * BLOCK < I.m) block_partials<3>(acc, I, I.ntiles + blockIdx.x);
 }
 
 // pair values m_k = C_ij + sum_{l in L_ij} y_l (A_l)_ij (Algorithm 4)
@@ -331,27 +319,30 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  const T lam2 = (T)(2.0 * P.lam), invL = (T)P.invL, Lc = (T)P.L;
+  const double lam2 = 2.0 * P.lam, invL = P.invL, Lc = P.L;
 
   for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
-    T w[NC];
+    // FP64 accumulation (also for FP32 data): near a stationary point the
+    // row sum cancels, and the FISTA / AIPP tests need the gradient to
+    // relative accuracy, not to the size of its terms
+    double w[NC];
 #pragma unroll
-    for (int e = 0; e < NC; ++e) w[e] = T(0);
+    for (int e = 0; e < NC; ++e) w[e] = 0.0;
     const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
     for (int k = k0 + strm; k < k1; k += (1 << plog)) {
       const int j = I.col_u[k];
-      const T mv = m[k];
+      const double mv = (double)m[k];
       const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
 #pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += mv * x.v[e];
+      for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
     }
     const int e0 = I.rowptr_l[i], e1 = I.rowptr_l[i + 1];
     for (int e2 = e0 + strm; e2 < e1; e2 += (1 << plog)) {
       const int j = I.col_l[e2];
-      const T mv = m[I.pid_l[e2]];
+      const double mv = (double)m[I.pid_l[e2]];
       const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
 #pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += mv * x.v[e];
+      for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
     }
     // reduce the pair streams (lanes ch + G*s)
     for (int o = TS / 2; o >= G; o >>= 1) {
@@ -360,15 +351,15 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
     }
     if (strm == 0) {
       for (int t = 0; t < r0; ++t) {
-        const T kv = K0[(size_t)i * r0 + t];
+        const double kv = (double)K0[(size_t)i * r0 + t];
 #pragma unroll
-        for (int e = 0; e < NC; ++e) w[e] += kv * (T)Z0[t * R_MAX + ch * NC + e];
+        for (int e = 0; e < NC; ++e) w[e] += kv * Z0[t * R_MAX + ch * NC + e];
       }
       const size_t off = (size_t)i * R + ch * NC;
       if (MODE == SP_PLAIN) {
         Chunk<T> o;
 #pragma unroll
-        for (int e = 0; e < NC; ++e) o.v[e] = w[e];
+        for (int e = 0; e < NC; ++e) o.v[e] = (T)w[e];
         stc(role_ptr<T>(I, P, a.outrole) + off, o);
       } else if (MODE == SP_TRIAL) {
         const Chunk<T> xi = ldc(X + off);
@@ -376,8 +367,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
         Chunk<T> gr, z;
 #pragma unroll
         for (int e = 0; e < NC; ++e) {
-          gr.v[e] = lam2 * w[e] + (xi.v[e] - w0.v[e]);
-          z.v[e] = xi.v[e] - gr.v[e] * invL;
+          const double g = lam2 * w[e] + ((double)xi.v[e] - (double)w0.v[e]);
+          gr.v[e] = (T)g;
+          z.v[e] = (T)((double)xi.v[e] - g * invL);
           acc[0] += (double)z.v[e] * (double)z.v[e];
         }
         stc(role_ptr<T>(I, P, RGR) + off, gr);
@@ -389,15 +381,15 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
         const Chunk<T> w0 = ldc(role_ptr<T>(I, P, RW0) + off);
 #pragma unroll
         for (int e = 0; e < NC; ++e) {
-          const double rl = (double)(lam2 * w[e] - gr.v[e] + Lc * (xt.v[e] - xi.v[e]));
+          const double rl = lam2 * w[e] - (double)gr.v[e] + Lc * ((double)xt.v[e] - (double)xi.v[e]);
           acc[0] += rl * rl;
-          acc[1] += rl * (double)(w0.v[e] - xi.v[e]);
-          acc[2] += (double)w[e] * (double)xi.v[e];
+          acc[1] += rl * ((double)w0.v[e] - (double)xi.v[e]);
+          acc[2] += w[e] * (double)xi.v[e];
         }
       }
     }
   }
-  if (MODE != SP_PLAIN) block_partials<NQ>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  if (MODE != SP_PLAIN) block_partials<NQ>(acc, I, tl.lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles,
     }
     stc(XTp + off, o);
   }
-  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<1>(acc, I, tl.lt);
 }
 
 // y+ = c Z (projection onto the Frobenius ball, c from the reduce kernel),
@@ -477,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, 
     }
     stc(Zp + off, z);
   }
-  block_partials<3>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<3>(acc, I, tl.lt);
 }
 
 // Copy role src -> role dst (scaled), optional partial ||dst||^2.
@@ -505,7 +497,7 @@ __global__ __launch_bounds__(BLOCK) void k_copy_scale(const Tile *__restrict__ t
     }
     stc(D + off, x);
   }
-  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<1>(acc, I, tl.lt);
 }
 
 // Pack an external n x r (ld) FP64/op-type matrix into role dst (R columns,
@@ -527,7 +519,7 @@ __global__ __launch_bounds__(BLOCK) void k_pack(const Tile *__restrict__ tiles, 
     D[(size_t)i * R + c] = v;
     acc[0] += (double)v * (double)v;
   }
-  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<1>(acc, I, tl.lt);
 }
 
 template <typename T, int G, typename S>
@@ -607,11 +599,10 @@ __global__ __launch_bounds__(BLOCK) void k_gram(const Tile *__restrict__ tiles, 
     }
     __syncthreads();
   }
-  double *dst = I.gram + (size_t)tl.lt * R * R;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * BLOCK;
-    if (idx < R * R) dst[idx] = acc[q];
+    if (idx < R * R) I.gram[(size_t)idx * I.ntiles + tl.lt] = acc[q];
   }
 }
 
@@ -670,7 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_fw_den(const Tile *__restrict__ tiles
     }
   }
   (void)k0; (void)k1;
-  block_partials<1>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<1>(acc, I, tl.lt);
 }
 
 // general-mode denominator (per constraint)
@@ -689,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void k_fw_den_gen(const int32_t *__restrict_
     const double d = I.TY[l] - P.tau2 * t;
     acc[0] = d * d;
   }
-  if (blockIdx.x * BLOCK < I.m) block_partials<1>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+  if (blockIdx.x * BLOCK < I.m) block_partials<1>(acc, I, I.ntiles + blockIdx.x);
 }
 
 // p <- y'(Y) and partial b^T p (dual value), ||T(Y) - b||^2.
@@ -704,7 +695,7 @@ __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ili
     const double r = I.TY[l] - I.b[l];
     acc[1] = r * r;
   }
-  if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I.part + (size_t)(I.ntiles + blockIdx.x) * PSTRIDE);
+  if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I, I.ntiles + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -774,8 +765,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tile
     }
   }
   __syncthreads();
-  double *dst = I.part + (size_t)tl.lt * PSTRIDE;
-  for (int q = threadIdx.x; q < nq; q += BLOCK) dst[q] = lds[q];
+  for (int q = threadIdx.x; q < nq; q += BLOCK) I.part[(size_t)q * I.prows + tl.lt] = lds[q];
 }
 
 // w -= sum_q V_q h_q; in the final pass also partial ||w||^2 and K0^T w.
@@ -801,7 +791,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ ti
       for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
     }
   }
-  if (final_pass) block_partials<1 + LR_MAX>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  if (final_pass) block_partials<1 + LR_MAX>(acc, I, tl.lt);
 }
 
 // v_{j+1} = w / beta_j (beta from the reduce kernel)
@@ -846,7 +836,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_start(const Tile *__restrict__ til
     acc[0] += wi * wi;
     for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
   }
-  block_partials<1 + LR_MAX>(acc, I.part + (size_t)tl.lt * PSTRIDE);
+  block_partials<1 + LR_MAX>(acc, I, tl.lt);
 }
 
 // V[dst] = sum_{q < nq} Vsrc_q S[q, c] for c < ncol (Ritz vectors / thick restart),
@@ -904,82 +894,88 @@ struct RedArgs {
   int32_t extra;  // number of constraint-major partial rows (general mode / set_p)
 };
 
-__device__ double sum_slot(const InstDev &I, int q, int first, int count, double *lds) {
-  // fixed-order block sum of part[(first + t) * PSTRIDE + q], t < count
-  double s = 0.0;
-  for (int t = threadIdx.x; t < count; t += BLOCK) s += I.part[(size_t)(first + t) * PSTRIDE + q];
-  s = wave_sum(s);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// Sums of slots [q0, q1) over partial rows [row0, row0 + nrows) into out[0..):
+// one wave per slot, lanes stride the rows with four accumulators, a fixed
+// wave reduction -- a fixed order for every instance.
+__device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nrows, double *out) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int q = q0 + wave; q < q1; q += nw) {
+    const double *src = I.part + (size_t)q * I.prows + row0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = lane;
+    for (; t + 192 < nrows; t += 256) {
+      s0 += src[t];
+      s1 += src[t + 64];
+      s2 += src[t + 128];
+      s3 += src[t + 192];
+    }
+    for (; t < nrows; t += 64) s0 += src[t];
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
+    if (lane == 0) out[q - q0] = s;
+  }
   __syncthreads();
-  if (lane == 0) lds[wave] = s;
-  __syncthreads();
-  double tot = 0.0;
-  for (int w = 0; w < BLOCK / 64; ++w) tot += lds[w];
-  return tot;
 }
 
-__device__ void lowrank_finish(const InstDev &I, int R, int zsel, double *lds, double *trace_out) {
-  // Y0 (r0 x R) from slots 3.., Z0 = D0 Y0, trace = Tr(D0 Y0 Y0^T)
+// Y0 (r0 x R) = K0^T X from slots 4.. (already summed in y0), Z0 = D0 Y0,
+// returns Tr(D0 Y0 Y0^T) (Algorithms 3 and 5 for the objective).
+__device__ double lowrank_finish(const InstDev &I, int R, int zsel, const double *y0) {
   const int r0 = I.r0;
   double *Z0 = I.Z0 + zsel * LR_MAX * R_MAX;
-  __shared__ double y0[LR_MAX * R_MAX];
-  for (int q = 0; q < r0 * R; ++q) {
-    const double s = sum_slot(I, 4 + q, 0, I.ntiles, lds);
-    if (threadIdx.x == 0) y0[q] = s;
+  for (int q = threadIdx.x; q < r0 * R_MAX; q += blockDim.x) {
+    const int t = q / R_MAX, c = q % R_MAX;
+    double s = 0.0;
+    if (c < R)
+      for (int u = 0; u < r0; ++u) s += I.D0[t * r0 + u] * y0[u * R + c];
+    Z0[q] = s;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int t = 0; t < r0; ++t)
-      for (int u = 0; u < r0; ++u) {
-        double d = 0.0;
-        for (int c = 0; c < R; ++c) d += y0[t * R + c] * y0[u * R + c];
-        tr += I.D0[t * r0 + u] * d;
-      }
-    for (int t = 0; t < r0; ++t)
-      for (int c = 0; c < R_MAX; ++c) {
-        double s = 0.0;
-        if (c < R)
-          for (int u = 0; u < r0; ++u) s += I.D0[t * r0 + u] * y0[u * R + c];
-        Z0[t * R_MAX + c] = s;
-      }
-    *trace_out = tr;
-  }
-  __syncthreads();
+  double tr = 0.0;
+  for (int t = 0; t < r0; ++t)
+    for (int u = 0; u < r0; ++u) {
+      double d = 0.0;
+      for (int c = 0; c < R; ++c) d += y0[t * R + c] * y0[u * R + c];
+      tr += I.D0[t * r0 + u] * d;
+    }
+  return tr;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
-                                                  RedArgs a) {
-  __shared__ double lds[BLOCK / 64];
-  __shared__ double tr;
+__global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                   RedArgs a) {
+  __shared__ double S[PSTRIDE];
+  __shared__ double E[4];
   const InstDev &I = insts[ilist[blockIdx.x]];
   InstParams &P = *I.prm;
   double *res = I.res->v;
   const int nt = I.ntiles;
+  const int tid = threadIdx.x;
   switch (a.op) {
-    case RD_COMBO: {
-      const double s = sum_slot(I, 0, 0, nt, lds);
-      if (threadIdx.x == 0) res[S_XTW0] = s;
+    case RD_COMBO:
+    case RD_NORM:
+    case RD_TRIAL_PROJ: {
+      reduce_slots(I, 0, 1, 0, nt, S);
+      if (tid == 0) {
+        if (a.op == RD_COMBO) res[S_XTW0] = S[0];
+        else if (a.op == RD_NORM) res[S_NZ] = S[0];
+        else {
+          res[S_NZ] = S[0];
+          res[S_PROJC] = S[0] > P.tau2 ? P.tau / sqrt(S[0]) : 1.0;
+        }
+      }
       break;
     }
     case RD_SDDMM_XT:
     case RD_SDDMM_YP:
     case RD_EVAL: {
-      double T0 = sum_slot(I, 0, 0, nt, lds);
-      double pr = sum_slot(I, 1, 0, nt, lds);
-      double rr = sum_slot(I, 2, 0, nt, lds);
-      double yt = sum_slot(I, 3, 0, nt, lds);
+      const int nlr = I.r0 * a.R;
+      reduce_slots(I, 0, 4 + nlr, 0, nt, S);
       const int ex = I.direct ? 0 : (I.m + BLOCK - 1) / BLOCK;
-      if (ex > 0) {
-        pr += sum_slot(I, 0, nt, ex, lds);
-        rr += sum_slot(I, 1, nt, ex, lds);
-        yt += sum_slot(I, 2, nt, ex, lds);
-      }
-      if (threadIdx.x == 0) tr = 0.0;
+      if (ex > 0) reduce_slots(I, 0, 3, nt, ex, E);
+      else if (tid < 4) E[tid] = 0.0;
       __syncthreads();
-      if (I.r0 > 0) lowrank_finish(I, a.R, a.op == RD_SDDMM_YP ? 1 : a.zsel, lds, &tr);
-      if (threadIdx.x == 0) {
-        const double t0 = T0 + tr;
+      const int zsel = a.op == RD_SDDMM_YP ? 1 : a.zsel;
+      double tr = 0.0;
+      if (I.r0 > 0) tr = lowrank_finish(I, a.R, zsel, S + 4);
+      if (tid == 0) {
+        const double t0 = S[0] + tr, pr = S[1] + E[0], rr = S[2] + E[1], yt = S[3] + E[2];
         const double g = t0 + pr + 0.5 * P.beta * rr;
         const int slot = a.op == RD_SDDMM_XT ? S_G_XT : (a.op == RD_SDDMM_YP ? S_G_YP : S_G_EVAL);
         res[slot] = g;
@@ -993,55 +989,43 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ il
       }
       break;
     }
-    case RD_TRIAL_PROJ: {
-      const double nz = sum_slot(I, 0, 0, nt, lds);
-      if (threadIdx.x == 0) {
-        res[S_NZ] = nz;
-        res[S_PROJC] = nz > P.tau2 ? P.tau / sqrt(nz) : 1.0;
-      }
-      break;
-    }
-    case RD_PROJ_DOTS: {
-      const double a0 = sum_slot(I, 0, 0, nt, lds);
-      const double a1 = sum_slot(I, 1, 0, nt, lds);
-      const double a2 = sum_slot(I, 2, 0, nt, lds);
-      if (threadIdx.x == 0) {
-        res[S_GR_D] = a0;
-        res[S_D2] = a1;
-        res[S_YPW0] = a2;
-      }
-      break;
-    }
+    case RD_PROJ_DOTS:
     case RD_AIPP: {
-      const double a0 = sum_slot(I, 0, 0, nt, lds);
-      const double a1 = sum_slot(I, 1, 0, nt, lds);
-      const double a2 = sum_slot(I, 2, 0, nt, lds);
-      if (threadIdx.x == 0) {
-        res[S_RL2] = a0;
-        res[S_RL_W0] = a1;
-        res[S_WY] = a2;
+      reduce_slots(I, 0, 3, 0, nt, S);
+      if (tid == 0) {
+        if (a.op == RD_PROJ_DOTS) {
+          res[S_GR_D] = S[0];
+          res[S_D2] = S[1];
+          res[S_YPW0] = S[2];
+        } else {
+          res[S_RL2] = S[0];
+          res[S_RL_W0] = S[1];
+          res[S_WY] = S[2];
+        }
       }
       break;
     }
     case RD_LRONLY: {
-      if (I.r0 > 0) lowrank_finish(I, a.R, a.zsel, lds, &tr);
+      reduce_slots(I, 4, 4 + I.r0 * a.R, 0, nt, S);
+      if (I.r0 > 0) (void)lowrank_finish(I, a.R, a.zsel, S);
       break;
     }
-    case RD_NORM: {
-      const double s = sum_slot(I, 0, 0, nt, lds);
-      if (threadIdx.x == 0) res[S_NZ] = s;
-      break;
-    }
-    case RD_LZ_START: {
-      const double nrm2 = sum_slot(I, 0, 0, nt, lds);
-      double kw[LR_MAX] = {0.0, 0.0};
-      for (int t = 0; t < I.r0; ++t) kw[t] = sum_slot(I, 1 + t, 0, nt, lds);
-      if (threadIdx.x == 0) {
-        const double b = sqrt(nrm2);
+    case RD_LZ_START:
+    case RD_LZ_FINAL: {
+      if (a.op == RD_LZ_FINAL && P.lz_steps <= 0) break;
+      reduce_slots(I, 0, 1 + I.r0, 0, nt, S);
+      if (tid == 0) {
+        const double b = sqrt(S[0]);
         res[S_LZ_BETA] = b;
-        res[S_LZ_NRM0] = b;
-        for (int t = 0; t < I.r0; ++t) res[S_LZ_KV0 + t] = b > 0 ? kw[t] / b : 0.0;
-        P.lz_j = 0;
+        for (int t = 0; t < I.r0; ++t) res[S_LZ_KV0 + t] = b > 0 ? S[1 + t] / b : 0.0;
+        if (a.op == RD_LZ_START) {
+          res[S_LZ_NRM0] = b;
+          P.lz_j = 0;
+        } else {
+          I.dl_base[P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2) + KMAX + 1] = b;
+          P.lz_j += 1;
+          P.lz_steps -= 1;
+        }
       }
       break;
     }
@@ -1049,54 +1033,40 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ il
     case RD_LZ_H2: {
       if (P.lz_steps <= 0) break;
       const int nq = P.lz_j + 1;
-      // thread q sums slot q over tiles (fixed order)
+      reduce_slots(I, 0, nq, 0, nt, S);
       double *Hc = I.dl_base + P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2);
-      for (int q = threadIdx.x; q < nq; q += BLOCK) {
-        double s = 0.0;
-        for (int t = 0; t < nt; ++t) s += I.part[(size_t)t * PSTRIDE + q];
-        I.hcoef[q] = s;
-        if (a.op == RD_LZ_H1) Hc[q] = s;
-        else Hc[q] += s;
-      }
-      break;
-    }
-    case RD_LZ_FINAL: {
-      if (P.lz_steps <= 0) break;
-      const double nrm2 = sum_slot(I, 0, 0, nt, lds);
-      double kw[LR_MAX] = {0.0, 0.0};
-      for (int t = 0; t < I.r0; ++t) kw[t] = sum_slot(I, 1 + t, 0, nt, lds);
-      if (threadIdx.x == 0) {
-        const double b = sqrt(nrm2);
-        res[S_LZ_BETA] = b;
-        I.dl_base[P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2) + KMAX + 1] = b;
-        for (int t = 0; t < I.r0; ++t) res[S_LZ_KV0 + t] = b > 0 ? kw[t] / b : 0.0;
-        P.lz_j += 1;
-        P.lz_steps -= 1;
+      for (int q = tid; q < nq; q += blockDim.x) {
+        I.hcoef[q] = S[q];
+        if (a.op == RD_LZ_H1) Hc[q] = S[q];
+        else Hc[q] += S[q];
       }
       break;
     }
     case RD_FW_DEN: {
-      double s = sum_slot(I, 0, 0, nt, lds);
-      if (!I.direct) s += sum_slot(I, 0, nt, (I.m + BLOCK - 1) / BLOCK, lds);
-      if (threadIdx.x == 0) res[S_FWDEN] = s;
+      reduce_slots(I, 0, 1, 0, nt, S);
+      const int ex = I.direct ? 0 : (I.m + BLOCK - 1) / BLOCK;
+      if (ex > 0) reduce_slots(I, 0, 1, nt, ex, E);
+      if (tid == 0) res[S_FWDEN] = S[0] + (ex > 0 ? E[0] : 0.0);
       break;
     }
     case RD_SETP: {
       const int ex = (I.m + BLOCK - 1) / BLOCK;
-      const double bp = sum_slot(I, 0, nt, ex, lds);
-      const double rr = sum_slot(I, 1, nt, ex, lds);
-      if (threadIdx.x == 0) {
-        res[S_BP] = bp;
-        res[S_RR] = rr;
+      if (ex > 0) reduce_slots(I, 0, 2, nt, ex, E);
+      if (tid == 0) {
+        res[S_BP] = ex > 0 ? E[0] : 0.0;
+        res[S_RR] = ex > 0 ? E[1] : 0.0;
       }
       break;
     }
     case RD_GRAM: {
       const int R = a.R;
-      for (int q = threadIdx.x; q < R * R; q += BLOCK) {
+      const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+      for (int q = wave; q < R * R; q += nw) {
+        const double *src = I.gram + (size_t)q * nt;
         double s = 0.0;
-        for (int t = 0; t < nt; ++t) s += I.gram[(size_t)t * R * R + q];
-        I.dl_base[P.dl_off + q] = s;  // Gram matrix, row-major R x R
+        for (int t = lane; t < nt; t += 64) s += src[t];
+        s = wave_sum(s);
+        if (lane == 0) I.dl_base[P.dl_off + q] = s;  // Gram matrix, row-major R x R
       }
       break;
     }
@@ -1352,7 +1322,7 @@ void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstD
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra) {
   if (ni <= 0) return;
   RedArgs a{op, zsel, R, extra};
-  hipLaunchKernelGGL(k_reduce, dim3(ni), dim3(BLOCK), 0, s, ilist, d, a);
+  hipLaunchKernelGGL(k_reduce, dim3(ni), dim3(RBLOCK), 0, s, ilist, d, a);
 }
 void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_start, dim3(nt), dim3(BLOCK), 0, s, t, d);

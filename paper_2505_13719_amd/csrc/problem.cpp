@@ -232,12 +232,13 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
   return "";
 }
 
-// Tile schedule: contiguous row ranges holding about kTileWork units of
-// work (pairs + rows), at most kMaxTiles per instance, and per tile the
-// number of pair streams per row (power of two near the mean row length)
-// for the SDDMM (upper rows) and the SpMM (upper + lower rows).  Depends on
-// the instance only, so a batched instance reduces in the same order as a
-// standalone one.
+// Tile schedule: contiguous row ranges closed at kTileWork units of work
+// (pairs + rows) or at the row target, with at most about kMaxTiles tiles
+// per instance, and per tile the number of pair streams per row (power of
+// two near the mean row length) for the SDDMM (upper rows) and the SpMM
+// (upper + lower rows).  Small instances get short tiles so that a launch
+// has many workgroups; the schedule depends on the instance only, so a
+// batched instance reduces in the same order as a standalone one.
 static int plog_for(double avg) {
   int pl = 0;
   while ((1 << pl) < avg && pl < 6) ++pl;
@@ -245,23 +246,22 @@ static int plog_for(double avg) {
 }
 
 void build_tiles(HostProblem &hp) {
-  constexpr int64_t kTileWork = 4096;
+  constexpr int64_t kTileWork = 2048;
   constexpr int64_t kMaxTiles = 2048;
-  constexpr int32_t kMaxRows = 1024;
+  constexpr int32_t kMinRows = 16;
   const int32_t n = hp.n;
   const int64_t total = hp.npairs + hp.nlower + n;
-  const int64_t target = std::max<int64_t>(kTileWork, (total + kMaxTiles - 1) / kMaxTiles);
+  const int64_t work_target = std::max<int64_t>(kTileWork, (total + kMaxTiles - 1) / kMaxTiles);
+  const int32_t row_target = std::max<int32_t>(kMinRows, (int32_t)((n + kMaxTiles - 1) / kMaxTiles));
   hp.tiles.clear();
   int32_t r0 = 0;
   while (r0 < n) {
     int64_t work = 0;
     int32_t r1 = r0;
-    while (r1 < n && (r1 - r0) < kMaxRows && work < target) {
+    while (r1 < n && (r1 - r0) < row_target && work < work_target) {
       work += 1 + (hp.rowptr_u[r1 + 1] - hp.rowptr_u[r1]) + (hp.rowptr_l[r1 + 1] - hp.rowptr_l[r1]);
       ++r1;
     }
-    // keep tiles a multiple of 64 rows where possible (whole waves in vector kernels)
-    if (r1 < n && (r1 - r0) > 64) r1 = r0 + ((r1 - r0) / 64) * 64;
     const double rows = (double)(r1 - r0);
     const double up = (double)(hp.rowptr_u[r1] - hp.rowptr_u[r0]) / rows;
     const double sym = up + (double)(hp.rowptr_l[r1] - hp.rowptr_l[r0]) / rows;

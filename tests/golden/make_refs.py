@@ -1,6 +1,7 @@
-"""Write tests/golden/refs.json: FP64 oracle solves (eps = 1e-7) of the
-seeded workloads the GPU solve tests compare against.  Calls only oracle/
-and the instance generators."""
+"""Write tests/golden/refs.json: FP64 oracle solves of the seeded workloads
+the GPU solve tests compare against (eps = 1e-7, or 1e-6 where the oracle's
+iteration caps stop it before 1e-7).  Calls only oracle/ and the instance
+generators.  Usage: python tests/golden/make_refs.py [case ...]"""
 import json
 import os
 import sys
@@ -16,28 +17,31 @@ import sdp_instances as si  # noqa: E402
 
 
 def cases():
-    yield "maxcut_er800_s1", si.maxcut_er_800(1), dict(rank_cap=16)
+    yield "maxcut_er800_s1", si.maxcut_er_800(1), dict(rank_cap=16), 1e-7
     rng = np.random.default_rng(11)
     i, j = si.er_edges(400, 0.02, rng)
-    yield "maxcut_pm1_er400", si.maxcut_problem(400, i, j, si.pm1_weights(i.size, rng), name="maxcut_pm1_er400"), {}
-    yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}
+    yield "maxcut_pm1_er400", si.maxcut_problem(400, i, j, si.pm1_weights(i.size, rng), name="maxcut_pm1_er400"), {}, 1e-7
+    yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}, 1e-6
     rng = np.random.default_rng(12)
-    i, j = si.er_edges(300, 0.03, rng)
-    yield "theta_er300", si.theta_problem(300, i, j), {}
-    yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}
+    i, j = si.er_edges(150, 0.06, rng)
+    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-7
+    yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}, 1e-7
 
 
-def main():
-    out = {}
-    for name, prob, kw in cases():
+def main(only):
+    path = os.path.join(os.path.dirname(__file__), "refs.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    for name, prob, kw, eps in cases():
+        if only and name not in only:
+            continue
         t = time.time()
-        r = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=1e-7, time_limit=1800, **kw))
-        out[name] = dict(pval=r.pval, dval=r.dval, status=r.status, rank=r.rank, eps=1e-7, opts=kw,
+        r = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=eps, time_limit=1800, **kw))
+        out[name] = dict(pval=r.pval, dval=r.dval, status=r.status, rank=r.rank, eps=eps, opts=kw,
                          seconds=round(time.time() - t, 1))
         print(name, out[name], flush=True)
-    with open(os.path.join(os.path.dirname(__file__), "refs.json"), "w") as f:
-        json.dump(out, f, indent=1, sort_keys=True)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])
