@@ -119,7 +119,7 @@ def bench_solve(args):
     if args.precision:
         prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
     dev = torch.device("cuda:0")
-    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, **kw)
+    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, verbose=args.verbose, **kw)
     t_build = time.perf_counter()
     h = H.hallar_create(prob, prec, opts)
     t_build = time.perf_counter() - t_build
@@ -239,6 +239,7 @@ def main():
     ap.add_argument("--workload", default="torus", choices=["torus", "er800", "theta", "mc", "served"])
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", type=int, default=0, help="solver progress on stderr (1: outer, 2: HLR)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--served-requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")

@@ -274,7 +274,7 @@ def hallar(prob, U0, opts: Options = None, p0=None):
     tau = math.sqrt(prob.tau2)
     rng = np.random.default_rng(opts.seed)
     counters = dict(sddmm=0, spmm=0, matvec=0, fista_trials=0, aipp_iters=0,
-                    lam_halvings=0, hlr_iters=0, eig_calls=0, truncations=0)
+                    lam_halvings=0, hlr_iters=0, eig_calls=0, truncations=0, aipp_caps=0)
     cn1 = c_l1_norm(prob)
     U = _proj_ball(np.asarray(U0, np.float64).reshape(n, -1), tau)   # U_0 in B_tau
     p = np.zeros(prob.m) if p0 is None else np.asarray(p0, np.float64).copy()
@@ -299,9 +299,14 @@ def hallar(prob, U0, opts: Options = None, p0=None):
         for _ in range(opts.hlr_max_iter):
             counters["hlr_iters"] += 1
             st, Y, R, lam, gY = aipp(g, Yt, gY, min(lam * opts.lam_grow, opts.lam0), rho, opts, tau, counters)
-            if st != "ok":
+            if st == "numerical":
                 status = st
                 break
+            # st == "iter_limit": the safeguard on ADAP-AIPP's iterations (the
+            # paper's method has none) hands back its last iterate, which the
+            # Frank-Wolfe certificate below then judges like any other
+            if st != "ok":
+                counters["aipp_caps"] += 1
             if Y.shape[1] > 1:
                 Y = _compress(Y, opts.drop_tol)
             # G = C + A*(p + beta (A(YY^T) - b)) (eq. Grad X Space)

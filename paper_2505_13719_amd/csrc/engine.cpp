@@ -488,11 +488,12 @@ static void launch_group(Pool &P, const Group &g) {
   const GroupBytes B = P.profile ? group_bytes(P, g.slots, R) : GroupBytes{};
   const double sz = prec == 0 ? 8.0 : 4.0;
   double msum = 0, psum = 0;
-  if (P.profile)
-    for (int s : g.slots) {
-      msum += P.slots[s]->hp.m;
-      psum += (double)P.slots[s]->hp.npairs;
-    }
+  bool any_lr = false;
+  for (int s : g.slots) {
+    msum += P.slots[s]->hp.m;
+    psum += (double)P.slots[s]->hp.npairs;
+    any_lr = any_lr || P.slots[s]->hp.r0 > 0;
+  }
   auto red = [&](int op, int zsel) {
     ProfScope ps(P, KC_REDUCE, 0.0);
     op_reduce(st, IL, ni, D, op, zsel, R, 0);
@@ -500,7 +501,7 @@ static void launch_group(Pool &P, const Group &g) {
   auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
     {
       ProfScope ps(P, KC_SDDMM, B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0));
-      op_lr_dots(prec, R, st, T, nt, D, xrole);
+      if (any_lr) op_lr_dots(prec, R, st, T, nt, D, xrole);
       op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
       if (gni > 0) {
         op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
@@ -802,8 +803,15 @@ static bool finite(double x) { return std::isfinite(x); }
 struct FistaOut {
   int status = 0;  // 0 ok, 1 fail, 2 numerical
   int W = -1;
-  double L = 0, gW = 0, rl2 = 0, vdot = 0, dW2 = 0, wy = 0;
+  double L = 0, gW = 0, rl2 = 0, vdot = 0, dW2 = 0, wy = 0, gr2 = 0;
 };
+
+// Unit roundoff of the storage type of U and of the gradient buffer.  Function
+// values are exact for the stored iterates (products accumulate in FP64), but
+// the stored gradient GR is rounded to this precision, so an inner product
+// <GR, d> carries an error of at most u ||GR|| ||d||; the tests below allow
+// for it (negligible in FP64).
+static double storage_eps(int prec) { return prec == 0 ? 0x1p-53 : 0x1p-24; }
 
 // ADAP-FISTA (Appendix A.1) on psi_s = lam g + 1/2 ||. - x0||^2 over B_tau.
 static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
@@ -858,7 +866,8 @@ static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
         goto cleanup;
       }
       const double psx = lam * g_xt + 0.5 * xtw0, psy = lam * g_yp + 0.5 * ypw0;
-      if (psx + gr_d + 0.25 * (1.0 - chi) * L * d2 >= psy) {
+      const double slack = 4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(c.res(S_GR2T), 0.0) * std::max(d2, 0.0));
+      if (psx + gr_d + 0.25 * (1.0 - chi) * L * d2 >= psy - slack) {
         accepted = true;
         break;
       }
@@ -897,6 +906,7 @@ static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
         out.dW2 = ypw0;
         out.vdot = c.res(S_RL_W0) - ypw0;  // <V, x0 - y+> with V = Rl - (x0 - y+)
         out.wy = c.res(S_WY);
+        out.gr2 = c.res(S_GR2A);
         goto cleanup;
       }
       if (y != x0) c.release(y);
@@ -934,6 +944,8 @@ static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out)
     for (;;) {
       const double Mj = std::max(1.0, 0.5 * Mbar);
       co_await fista(c, Wprev, lam, Mj, fo);
+      if (c.o.verbose >= 3 && fo.status != 0)
+        fprintf(stderr, "[hallar]     aipp j=%d fista status=%d lam=%.3g\n", j, fo.status, lam);
       if (fo.status == 2) {
         out.status = 2;
         out.W = Wprev;
@@ -941,7 +953,9 @@ static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out)
       }
       if (fo.status == 0) {
         const double lhs = lam * gprev - (lam * fo.gW + 0.5 * fo.dW2);
-        if (lhs >= fo.vdot - 1e-13 * (1.0 + std::fabs(lam * gprev))) break;
+        const double slack = 1e-13 * (1.0 + std::fabs(lam * gprev)) +
+                             4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(fo.gr2, 0.0) * std::max(fo.dW2, 0.0));
+        if (lhs >= fo.vdot - slack) break;
         c.release(fo.W);
       }
       lam *= 0.5;
@@ -952,11 +966,16 @@ static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out)
       }
     }
     const double Rn = std::sqrt(std::max(fo.rl2, 0.0)) / lam;
+    // R_j is resolved only down to the rounding of the stored gradient
+    const double Rfloor = 4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(fo.gr2, 0.0)) / lam;
     Mbar = fo.L;
     c.release(Wprev);
     Wprev = fo.W;
     gprev = fo.gW;
-    if (Rn <= rho) {
+    if (c.o.verbose >= 3)
+      fprintf(stderr, "[hallar]     aipp j=%d lam=%.3g Rn=%.3e rho=%.3e floor=%.3e L=%.3g g=%.12g\n", j, lam, Rn, rho,
+              Rfloor, fo.L, gprev);
+    if (Rn <= std::max(rho, Rfloor)) {
       out.status = 0;
       out.W = Wprev;
       out.lam = lam;
@@ -1178,10 +1197,12 @@ static Task solve_main(Ctx c) {
       lam = ao.lam;
       if (ao.status != 0 && o.verbose >= 2)
         fprintf(stderr, "[hallar]   aipp failed t=%d it=%d status=%d lam=%.3g rank=%d rho=%.3e\n", t, it, ao.status, ao.lam, r, rho);
-      if (ao.status != 0) {
-        res.status = ao.status == 2 ? HALLAR_E_NUMERICAL : HALLAR_E_ITER_LIMIT;
+      if (ao.status == 2) {
+        res.status = HALLAR_E_NUMERICAL;
         break;
       }
+      // ao.status == 1: ADAP-AIPP's iteration safeguard (the paper's method has
+      // none) returns its last iterate; the Frank-Wolfe certificate judges it
       if (r > 1) {
         bool tr = false;
         co_await compress(c, Y, r, 0, tr);

@@ -21,6 +21,8 @@ constexpr int R_MAX = 64;        // columns of U
 constexpr int KMAX = 64;         // Lanczos basis vectors before a restart
 constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR_MAX, >= 3 + LR_MAX * R_MAX)
 constexpr int NRES = 32;         // result scalars per instance
+constexpr int TILE_MAX_ROWS = 1024;     // rows of a tile (row pointers staged in LDS)
+constexpr int TILE_MAX_ENTRIES = 2048;  // entries of S u S^T staged per tile (longer tiles: single rows)
 
 // Roles of the n x R work buffers (operator type).  The host maps roles to
 // physical buffers per instance (InstParams::buf), so FISTA's y <- y+ and
@@ -76,6 +78,8 @@ enum ResSlot : int {
   S_FWDEN, S_LZ_BETA, S_LZ_NRM0, S_LZ_ALPHA, S_GRAM_OK, S_NAN,
   S_LZ_KV0, S_LZ_KV1,   // K0^T v for the next SpMV (low-rank term)
   S_YT,                 // sum_l y'_l T_l (G . XX^T = T_0 + sum_l y'_l T_l)
+  S_GR2T,               // ||GR||^2 of a FISTA trial (rounding bound of <GR, d>)
+  S_GR2A,               // ||GR||^2 at ADAP-FISTA's output (rounding bound of R_j)
   S_COUNT
 };
 

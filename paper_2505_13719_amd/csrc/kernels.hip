@@ -72,6 +72,17 @@ __device__ __forceinline__ T *role_ptr(const InstDev &I, const InstParams &P, in
   return reinterpret_cast<T *>(I.buf[P.buf[role]]);
 }
 
+
+// Tile of this workgroup.  The hardware deals workgroups to the 8 XCDs in
+// turn (workgroup b to XCD b mod 8); this bijection gives each XCD a
+// contiguous run of tiles, so neighbouring rows gathered by the sparse
+// kernels stay in that XCD's L2.
+__device__ __forceinline__ int tile_index() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
+  return x * q + min(x, rem) + k;
+}
+
 // ---------------------------------------------------------------------------
 // SDDMM: T_l = A_l . XX^T over the pairs of S (Algorithm 2, eq. omega:
 // weight (2 - delta_ij) A_ij), T_0 = C . XX^T with the low-rank part
@@ -92,66 +103,109 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
                                                  SddmmArgs a) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  constexpr int NQ = 4;  // T0, p^T r, ||r||^2, sum y' T
-  const Tile tl = tiles[blockIdx.x];
+  constexpr int NQ = 4;          // T0, p^T r, ||r||^2, sum y' T
+  constexpr int PPP = BLOCK / G;  // pairs per pass (one G-lane group per pair)
+  constexpr int UN = G < 4 ? G : 4;
+  // The tile's pairs are taken in batches of BLOCK: (A) one thread per pair
+  // loads its row (search in the tile's row pointers), column and epilogue
+  // operands; (B) G-lane groups form the dot products, UN pairs per group in
+  // flight; (C) one thread per pair applies the epilogue.
+  __shared__ int32_t s_rp[TILE_MAX_ROWS + 1];
+  __shared__ int32_t s_i[BLOCK], s_j[BLOCK];
+  __shared__ double s_d[BLOCK];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
-  constexpr int LOGG = G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
-  const int plog = min((int)tl.plog_u, 6 - LOGG);  // team of G << plog <= 64 lanes
-  const int TS = G << plog;
-  const int team = threadIdx.x / TS;
-  const int lt = threadIdx.x - team * TS;
-  const int strm = lt / G, ch = lt - (lt / G) * G;
-  const int nteams = BLOCK / TS;
   const T *__restrict__ cu = reinterpret_cast<const T *>(I.c_u);
   const T *__restrict__ pa = reinterpret_cast<const T *>(I.pa);
   T *mout = a.msel == 0 ? reinterpret_cast<T *>(I.m_xt) : (a.msel == 1 ? reinterpret_cast<T *>(I.m_yp) : nullptr);
   const double beta = P.beta;
   const int direct = I.direct;
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) s_rp[r] = I.rowptr_u[tl.row0 + r];
+  __syncthreads();
+  const int kbeg = s_rp[0], kend = s_rp[nrows];
+  const int ch = threadIdx.x % G, grp = threadIdx.x / G;
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
-  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
-    const Chunk<T> ui = ldc(X + (size_t)i * R + ch * NC);
-    const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
-    for (int k = k0 + strm; k < k1; k += (1 << plog)) {
-      const int j = I.col_u[k];
-      const Chunk<T> uj = ldc(X + (size_t)j * R + ch * NC);
-      // products accumulate in FP64 (also for FP32 U): the AL value that the
-      // FISTA / AIPP tests compare must be exact for the stored iterate
-      double d = 0.0;
-#pragma unroll
-      for (int e = 0; e < NC; ++e) d += (double)ui.v[e] * (double)uj.v[e];
-      d = group_sum<G>(d);
-      if (ch == 0) {
-        const double B = d;
-        const double w2 = (i == j) ? 1.0 : 2.0;
-        const double cv = cu ? (double)cu[k] : 0.0;
-        acc[0] += w2 * cv * B;
-        if (direct) {
-          const int l = I.pcon[k];
-          double mv = cv;
-          if (l > 0) {
-            const double av = (double)pa[k];
-            const double t = w2 * av * B;
-            const double r = t - I.b[l - 1];
-            const double pl = I.p[l - 1];
-            const double y = pl + beta * r;
-            acc[1] += pl * r;
-            acc[2] += r * r;
-            acc[3] += y * t;
-            if (a.write_T) I.TY[l - 1] = t;
-            if (a.write_yp) I.yp[l - 1] = y;
-            mv = cv + av * y;
-          }
-          if (mout) mout[k] = (T)mv;
-        } else {
-          I.Bpair[k] = B;
+  for (int kb = kbeg; kb < kend; kb += BLOCK) {
+    const int k = kb + threadIdx.x;
+    const bool valid = k < kend;
+    int l = 0;
+    double cv = 0.0, av = 0.0, bl = 0.0, pl = 0.0;
+    if (valid) {
+      int lo = 0, hi = nrows - 1;  // last row whose first pair is <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      s_i[threadIdx.x] = tl.row0 + lo;
+      s_j[threadIdx.x] = I.col_u[k];
+      cv = cu ? (double)cu[k] : 0.0;
+      if (direct) {
+        l = I.pcon[k];
+        if (l > 0) {
+          av = (double)pa[k];
+          bl = I.b[l - 1];
+          pl = I.p[l - 1];
         }
       }
     }
+    __syncthreads();
+    const int nb = min(BLOCK, kend - kb);
+    for (int ps = 0; ps < G; ps += UN) {
+      Chunk<T> ci[UN], cj[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int pb = (ps + u) * PPP + grp;
+        if (pb < nb) {
+          ci[u] = ldc(X + (size_t)s_i[pb] * R + ch * NC);
+          cj[u] = ldc(X + (size_t)s_j[pb] * R + ch * NC);
+        } else {
+#pragma unroll
+          for (int e = 0; e < NC; ++e) ci[u].v[e] = cj[u].v[e] = T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        // products accumulate in FP64 (also for FP32 U): the AL value that the
+        // FISTA / AIPP tests compare must be exact for the stored iterate
+        double d = 0.0;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) d += (double)ci[u].v[e] * (double)cj[u].v[e];
+        d = group_sum<G>(d);
+        const int pb = (ps + u) * PPP + grp;
+        if (ch == 0 && pb < nb) s_d[pb] = d;
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      const double B = s_d[threadIdx.x];
+      const double w2 = (s_i[threadIdx.x] == s_j[threadIdx.x]) ? 1.0 : 2.0;
+      acc[0] += w2 * cv * B;
+      if (direct) {
+        double mv = cv;
+        if (l > 0) {
+          const double t = w2 * av * B;
+          const double r = t - bl;
+          const double y = pl + beta * r;
+          acc[1] += pl * r;
+          acc[2] += r * r;
+          acc[3] += y * t;
+          if (a.write_T) I.TY[l - 1] = t;
+          if (a.write_yp) I.yp[l - 1] = y;
+          mv = cv + av * y;
+        }
+        if (mout) mout[k] = (T)mv;
+      } else {
+        I.Bpair[k] = B;
+      }
+    }
+    __syncthreads();  // s_i, s_j, s_d are rewritten by the next batch
   }
   block_partials<NQ>(acc, I, tl.lt);
 }
@@ -164,7 +218,7 @@ __global__ __launch_bounds__(BLOCK) void k_lr_dots(const Tile *__restrict__ tile
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
   __shared__ double lds[(BLOCK / 64) * PSTRIDE];
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *__restrict__ X = role_ptr<T>(I, P, xrole);
@@ -281,10 +335,10 @@ __global__ __launch_bounds__(BLOCK) void k_pairvals(const int32_t *__restrict__ 
 // (Algorithms 4 and 5) with epilogues:
 //   PLAIN: store W (role out).
 //   TRIAL: GR = 2 lam W + X - W0 (grad of psi_s = lam g + 1/2||. - W0||^2,
-//          eq. Grad U Space), Z = X - GR / L, partial ||Z||^2.
+//          eq. Grad U Space), Z = X - GR / L, partial ||Z||^2, ||GR||^2.
 //   AIPP:  X = y+, GR = grad psi_s(x~): Rl = 2 lam W - GR + L (XT - X)
 //          = V + W0 - y+ (V of ADAP-FISTA's output), partial ||Rl||^2,
-//          <Rl, W0 - X>, <W, X> (= G . XX^T).
+//          <Rl, W0 - X>, <W, X> (= G . XX^T), ||GR||^2.
 // ---------------------------------------------------------------------------
 enum SpmmMode : int { SP_PLAIN = 0, SP_TRIAL = 1, SP_AIPP = 2 };
 
@@ -295,97 +349,185 @@ struct SpmmArgs {
   int32_t outrole;
 };
 
+// operands of the row epilogue, loaded before the row's products so that
+// their latency overlaps the gathers
+template <typename T>
+struct EpiIn {
+  Chunk<T> x, a, b, c;
+};
+
+template <typename T, int G, int MODE>
+__device__ __forceinline__ EpiIn<T> spmm_epi_load(const InstDev &I, const InstParams &P, const T *X, size_t off) {
+  EpiIn<T> in;
+  if (MODE == SP_TRIAL) {
+    in.x = ldc(X + off);
+    in.a = ldc(role_ptr<T>(I, P, RW0) + off);
+  } else if (MODE == SP_AIPP) {
+    in.x = ldc(X + off);
+    in.a = ldc(role_ptr<T>(I, P, RGR) + off);
+    in.b = ldc(role_ptr<T>(I, P, RXT) + off);
+    in.c = ldc(role_ptr<T>(I, P, RW0) + off);
+  }
+  return in;
+}
+
+template <typename T, int G, int MODE, int NQ>
+__device__ __forceinline__ void spmm_epi_apply(const InstDev &I, const InstParams &P, const SpmmArgs &a, int i, int ch,
+                                               double (&w)[NCh<T>::N], const EpiIn<T> &in, double (&acc)[NQ]) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const int r0 = I.r0;
+  const T *__restrict__ K0 = reinterpret_cast<const T *>(I.K0);
+  const double *Z0 = I.Z0 + a.zsel * LR_MAX * R_MAX;
+  for (int t = 0; t < r0; ++t) {
+    const double kv = (double)K0[(size_t)i * r0 + t];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) w[e] += kv * Z0[t * R_MAX + ch * NC + e];
+  }
+  const size_t off = (size_t)i * R + ch * NC;
+  if (MODE == SP_PLAIN) {
+    Chunk<T> o;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) o.v[e] = (T)w[e];
+    stc(role_ptr<T>(I, P, a.outrole) + off, o);
+  } else if (MODE == SP_TRIAL) {
+    const double lam2 = 2.0 * P.lam, invL = P.invL;
+    Chunk<T> gr, z;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      const double g = lam2 * w[e] + ((double)in.x.v[e] - (double)in.a.v[e]);
+      gr.v[e] = (T)g;
+      z.v[e] = (T)((double)in.x.v[e] - g * invL);
+      acc[0] += (double)z.v[e] * (double)z.v[e];
+      acc[1] += (double)gr.v[e] * (double)gr.v[e];
+    }
+    stc(role_ptr<T>(I, P, RGR) + off, gr);
+    stc(role_ptr<T>(I, P, RZ) + off, z);
+  } else {
+    const double lam2 = 2.0 * P.lam, Lc = P.L;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      const double rl = lam2 * w[e] - (double)in.a.v[e] + Lc * ((double)in.b.v[e] - (double)in.x.v[e]);
+      acc[0] += rl * rl;
+      acc[1] += rl * ((double)in.c.v[e] - (double)in.x.v[e]);
+      acc[2] += w[e] * (double)in.x.v[e];
+      acc[3] += (double)in.a.v[e] * (double)in.a.v[e];
+    }
+  }
+}
+
 template <typename T, int G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                 SpmmArgs a) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  constexpr int NQ = MODE == SP_AIPP ? 3 : (MODE == SP_TRIAL ? 1 : 1);
-  const Tile tl = tiles[blockIdx.x];
+  constexpr int NQ = MODE == SP_AIPP ? 4 : (MODE == SP_TRIAL ? 2 : 1);
+  constexpr int RPP = BLOCK / G;  // rows per pass (one G-lane group per row)
+  constexpr int UN = 8;           // gathers in flight per lane
+  __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
+  __shared__ int32_t s_col[TILE_MAX_ENTRIES];
+  __shared__ T s_m[TILE_MAX_ENTRIES];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
   const T *__restrict__ m = reinterpret_cast<const T *>(a.msel ? I.m_yp : I.m_xt);
-  constexpr int LOGG = G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
-  const int plog = min((int)tl.plog_s, 6 - LOGG);
-  const int TS = G << plog;
-  const int team = threadIdx.x / TS;
-  const int lt = threadIdx.x - team * TS;
-  const int strm = lt / G, ch = lt - (lt / G) * G;
-  const int nteams = BLOCK / TS;
-  const int r0 = I.r0;
-  const T *__restrict__ K0 = reinterpret_cast<const T *>(I.K0);
-  const double *Z0 = I.Z0 + a.zsel * LR_MAX * R_MAX;
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) {
+    s_ru[r] = I.rowptr_u[tl.row0 + r];
+    s_rl[r] = I.rowptr_l[tl.row0 + r];
+  }
+  __syncthreads();
+  const int ku0 = s_ru[0], nu = s_ru[nrows] - ku0;
+  const int kl0 = s_rl[0], nl = s_rl[nrows] - kl0;
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  const double lam2 = 2.0 * P.lam, invL = P.invL, Lc = P.L;
 
-  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
-    // FP64 accumulation (also for FP32 data): near a stationary point the
-    // row sum cancels, and the FISTA / AIPP tests need the gradient to
-    // relative accuracy, not to the size of its terms
-    double w[NC];
-#pragma unroll
-    for (int e = 0; e < NC; ++e) w[e] = 0.0;
-    const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
-    for (int k = k0 + strm; k < k1; k += (1 << plog)) {
-      const int j = I.col_u[k];
-      const double mv = (double)m[k];
-      const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
-#pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
+  if (nu + nl <= TILE_MAX_ENTRIES) {
+    // stage the tile's columns and pair values of S u S^T (upper part, then
+    // the lower transpose through its pair ids) with coalesced loads
+    for (int e = threadIdx.x; e < nu; e += BLOCK) {
+      s_col[e] = I.col_u[ku0 + e];
+      s_m[e] = m[ku0 + e];
     }
-    const int e0 = I.rowptr_l[i], e1 = I.rowptr_l[i + 1];
-    for (int e2 = e0 + strm; e2 < e1; e2 += (1 << plog)) {
-      const int j = I.col_l[e2];
-      const double mv = (double)m[I.pid_l[e2]];
-      const Chunk<T> x = ldc(X + (size_t)j * R + ch * NC);
-#pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
+    for (int e = threadIdx.x; e < nl; e += BLOCK) {
+      s_col[nu + e] = I.col_l[kl0 + e];
+      s_m[nu + e] = m[I.pid_l[kl0 + e]];
     }
-    // reduce the pair streams (lanes ch + G*s)
-    for (int o = TS / 2; o >= G; o >>= 1) {
+    __syncthreads();
+    const int ch = threadIdx.x % G, grp = threadIdx.x / G;
+    for (int rb = 0; rb < nrows; rb += RPP) {
+      const int r = rb + grp;
+      if (r >= nrows) continue;
+      const int i = tl.row0 + r;
+      const EpiIn<T> in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
+      const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
+      const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
+      // FP64 accumulation (also for FP32 data): near a stationary point the
+      // row sum cancels, and the FISTA / AIPP tests need the gradient to
+      // relative accuracy, not to the size of its terms
+      double w[NC];
 #pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
-    }
-    if (strm == 0) {
-      for (int t = 0; t < r0; ++t) {
-        const double kv = (double)K0[(size_t)i * r0 + t];
+      for (int e = 0; e < NC; ++e) w[e] = 0.0;
+      for (int q = 0; q < cnt; q += UN) {
+        Chunk<T> x[UN];
+        double mv[UN];
 #pragma unroll
-        for (int e = 0; e < NC; ++e) w[e] += kv * Z0[t * R_MAX + ch * NC + e];
+        for (int u = 0; u < UN; ++u) {
+          const int idx = q + u;
+          if (idx < cnt) {
+            const int pos = idx < cu ? a0 + idx : b0 + idx;
+            mv[u] = (double)s_m[pos];
+            x[u] = ldc(X + (size_t)s_col[pos] * R + ch * NC);
+          } else {
+            mv[u] = 0.0;
+#pragma unroll
+            for (int e = 0; e < NC; ++e) x[u].v[e] = T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+#pragma unroll
+          for (int e = 0; e < NC; ++e) w[e] += mv[u] * (double)x[u].v[e];
       }
-      const size_t off = (size_t)i * R + ch * NC;
-      if (MODE == SP_PLAIN) {
-        Chunk<T> o;
+      spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
+    }
+  } else {
+    // a tile too long to stage (one row of very high degree): teams of
+    // G << plog lanes, 2^plog pair streams per row, read from HBM
+    constexpr int LOGG = G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
+    const int plog = min((int)tl.plog_s, 6 - LOGG);
+    const int TS = G << plog;
+    const int team = threadIdx.x / TS;
+    const int lt = threadIdx.x - team * TS;
+    const int strm = lt / G, ch = lt - (lt / G) * G;
+    const int nteams = BLOCK / TS;
+    for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
+      double w[NC];
 #pragma unroll
-        for (int e = 0; e < NC; ++e) o.v[e] = (T)w[e];
-        stc(role_ptr<T>(I, P, a.outrole) + off, o);
-      } else if (MODE == SP_TRIAL) {
-        const Chunk<T> xi = ldc(X + off);
-        const Chunk<T> w0 = ldc(role_ptr<T>(I, P, RW0) + off);
-        Chunk<T> gr, z;
+      for (int e = 0; e < NC; ++e) w[e] = 0.0;
+      const int k0 = I.rowptr_u[i], k1 = I.rowptr_u[i + 1];
+      for (int k = k0 + strm; k < k1; k += (1 << plog)) {
+        const double mv = (double)m[k];
+        const Chunk<T> x = ldc(X + (size_t)I.col_u[k] * R + ch * NC);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) {
-          const double g = lam2 * w[e] + ((double)xi.v[e] - (double)w0.v[e]);
-          gr.v[e] = (T)g;
-          z.v[e] = (T)((double)xi.v[e] - g * invL);
-          acc[0] += (double)z.v[e] * (double)z.v[e];
-        }
-        stc(role_ptr<T>(I, P, RGR) + off, gr);
-        stc(role_ptr<T>(I, P, RZ) + off, z);
-      } else {
-        const Chunk<T> xi = ldc(X + off);
-        const Chunk<T> gr = ldc(role_ptr<T>(I, P, RGR) + off);
-        const Chunk<T> xt = ldc(role_ptr<T>(I, P, RXT) + off);
-        const Chunk<T> w0 = ldc(role_ptr<T>(I, P, RW0) + off);
+        for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
+      }
+      const int e0 = I.rowptr_l[i], e1 = I.rowptr_l[i + 1];
+      for (int e2 = e0 + strm; e2 < e1; e2 += (1 << plog)) {
+        const double mv = (double)m[I.pid_l[e2]];
+        const Chunk<T> x = ldc(X + (size_t)I.col_l[e2] * R + ch * NC);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) {
-          const double rl = lam2 * w[e] - (double)gr.v[e] + Lc * ((double)xt.v[e] - (double)xi.v[e]);
-          acc[0] += rl * rl;
-          acc[1] += rl * ((double)w0.v[e] - (double)xi.v[e]);
-          acc[2] += w[e] * (double)xi.v[e];
-        }
+        for (int e = 0; e < NC; ++e) w[e] += mv * (double)x.v[e];
+      }
+      for (int o = TS / 2; o >= G; o >>= 1) {
+#pragma unroll
+        for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
+      }
+      if (strm == 0) {
+        const EpiIn<T> in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
+        spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
       }
     }
   }
@@ -402,7 +544,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *Xp = role_ptr<T>(I, P, RX);
@@ -443,7 +585,7 @@ template <typename T, int G>
 __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   T *Zp = role_ptr<T>(I, P, RZ);
@@ -478,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) void k_copy_scale(const Tile *__restrict__ t
                                                       int32_t src, int32_t dst) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *S = role_ptr<T>(I, P, src);
@@ -507,7 +649,7 @@ __global__ __launch_bounds__(BLOCK) void k_pack(const Tile *__restrict__ tiles, 
                                                 const S *__restrict__ src, int32_t r, int64_t ld, int32_t dst, double scale) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   T *D = role_ptr<T>(I, P, dst);
@@ -527,7 +669,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpack(const Tile *__restrict__ tiles
                                                   S *__restrict__ out, int32_t r, int64_t ld, int32_t src) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *Sx = role_ptr<T>(I, P, src);
@@ -545,7 +687,7 @@ __global__ __launch_bounds__(BLOCK) void k_fw_apply(const Tile *__restrict__ til
                                                     int32_t src, int32_t dst) {
   constexpr int NC = NCh<T>::N;
   constexpr int RS = GS * NC, RD = GD * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *S = role_ptr<T>(I, P, src);
@@ -572,7 +714,7 @@ __global__ __launch_bounds__(BLOCK) void k_gram(const Tile *__restrict__ tiles, 
   constexpr int R = G * NC;
   constexpr int RB = 16;  // rows staged per step
   __shared__ double rows[RB][R];
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *S = role_ptr<T>(I, P, src);
@@ -612,7 +754,7 @@ __global__ __launch_bounds__(BLOCK) void k_rotate(const Tile *__restrict__ tiles
                                                   int32_t src, int32_t dst) {
   constexpr int NC = NCh<T>::N;
   constexpr int RS = GS * NC, RD = GD * NC;
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *S = role_ptr<T>(I, P, src);
@@ -634,7 +776,7 @@ __global__ __launch_bounds__(BLOCK) void k_rotate(const Tile *__restrict__ tiles
 // sum of (T(YY^T)_l - tau^2 T(vv^T)_l)^2 (denominator of eq. FW stepsize).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_fw_den(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const double *v = I.lzv;
@@ -704,29 +846,79 @@ __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ili
 __device__ __forceinline__ double *lz_basis(const InstDev &I, const InstParams &P) { return P.lz_basis ? I.V2 : I.V; }
 
 // w = G v_j with G = C + A*(y) in FP64 (pair values m64) plus the low-rank
-// term K0 D0 (K0^T v_j); partial v_j^T w is not needed (dots follow).
+// term K0 D0 (K0^T v_j); partial v_j^T w is not needed (dots follow).  The
+// tile's columns and pair values are staged in LDS (as in the SpMM); teams of
+// 2^max(0, plog - 2) lanes share a row, so each lane gathers about four
+// entries of v at once.
 __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                    int32_t from_lzv) {
-  const Tile tl = tiles[blockIdx.x];
+  __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
+  __shared__ int32_t s_col[TILE_MAX_ENTRIES];
+  __shared__ double s_m[TILE_MAX_ENTRIES];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   if (!from_lzv && P.lz_steps <= 0) return;
   const double *v = from_lzv ? I.lzv : lz_basis(I, P) + (size_t)P.lz_j * I.n;
-  const int plog = tl.plog_s;
-  const int TS = 1 << plog;
-  const int team = threadIdx.x >> plog;
-  const int strm = threadIdx.x & (TS - 1);
-  const int nteams = BLOCK >> plog;
   double kd[LR_MAX] = {0.0, 0.0};
   for (int t = 0; t < I.r0; ++t) {
     double s = 0.0;
     for (int u = 0; u < I.r0; ++u) s += I.D0[t * I.r0 + u] * I.res->v[S_LZ_KV0 + u];
     kd[t] = s;
   }
-  for (int i = tl.row0 + team; i < tl.row1; i += nteams) {
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) {
+    s_ru[r] = I.rowptr_u[tl.row0 + r];
+    s_rl[r] = I.rowptr_l[tl.row0 + r];
+  }
+  __syncthreads();
+  const int ku0 = s_ru[0], nu = s_ru[nrows] - ku0;
+  const int kl0 = s_rl[0], nl = s_rl[nrows] - kl0;
+  const bool staged = nu + nl <= TILE_MAX_ENTRIES;
+  if (staged) {
+    for (int e = threadIdx.x; e < nu; e += BLOCK) {
+      s_col[e] = I.col_u[ku0 + e];
+      s_m[e] = I.m64[ku0 + e];
+    }
+    for (int e = threadIdx.x; e < nl; e += BLOCK) {
+      s_col[nu + e] = I.col_l[kl0 + e];
+      s_m[nu + e] = I.m64[I.pid_l[kl0 + e]];
+    }
+    __syncthreads();
+  }
+  const int plog = staged ? max(0, (int)tl.plog_s - 2) : (int)tl.plog_s;
+  const int TS = 1 << plog;
+  const int team = threadIdx.x >> plog;
+  const int strm = threadIdx.x & (TS - 1);
+  const int nteams = BLOCK >> plog;
+  for (int r = team; r < nrows; r += nteams) {
+    const int i = tl.row0 + r;
     double w = 0.0;
-    for (int k = I.rowptr_u[i] + strm; k < I.rowptr_u[i + 1]; k += TS) w += I.m64[k] * v[I.col_u[k]];
-    for (int e = I.rowptr_l[i] + strm; e < I.rowptr_l[i + 1]; e += TS) w += I.m64[I.pid_l[e]] * v[I.col_l[e]];
+    if (staged) {
+      const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
+      const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
+      constexpr int UN = 4;
+      for (int q = strm * UN; q < cnt; q += TS * UN) {
+        double mv[UN], x[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const int idx = q + u;
+          if (idx < cnt) {
+            const int pos = idx < cu ? a0 + idx : b0 + idx;
+            mv[u] = s_m[pos];
+            x[u] = v[s_col[pos]];
+          } else {
+            mv[u] = 0.0;
+            x[u] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) w += mv[u] * x[u];
+      }
+    } else {
+      for (int k = I.rowptr_u[i] + strm; k < I.rowptr_u[i + 1]; k += TS) w += I.m64[k] * v[I.col_u[k]];
+      for (int e = I.rowptr_l[i] + strm; e < I.rowptr_l[i + 1]; e += TS) w += I.m64[I.pid_l[e]] * v[I.col_l[e]];
+    }
     for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
@@ -738,7 +930,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tile
 // partial dots: q < nq: <V_q, w>; if lr: K0^T w at slots nq.. (only for the final pass)
 __global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
   __shared__ double lds[(BLOCK / 64) * PSTRIDE];
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   if (P.lz_steps <= 0) return;
@@ -771,7 +963,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tile
 // w -= sum_q V_q h_q; in the final pass also partial ||w||^2 and K0^T w.
 __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                      int32_t final_pass) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   if (P.lz_steps <= 0) return;
@@ -796,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ ti
 
 // v_{j+1} = w / beta_j (beta from the reduce kernel)
 __global__ __launch_bounds__(BLOCK) void k_lz_scale(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   if (P.lz_steps < 0) return;
@@ -812,7 +1004,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_scale(const Tile *__restrict__ til
 // start vector: w = lzv (written by the host-side generator kernel), partial
 // ||w||^2 and K0^T w.
 __global__ __launch_bounds__(BLOCK) void k_lz_start(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const uint64_t seed = P.lz_seed;
@@ -843,7 +1035,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_start(const Tile *__restrict__ til
 // writing either the other basis (restart) or lzv (single Ritz vector).
 __global__ __launch_bounds__(BLOCK) void k_lz_combine(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                       int32_t to_lzv) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const double *Vs = lz_basis(I, P);
@@ -895,23 +1087,36 @@ struct RedArgs {
 };
 
 // Sums of slots [q0, q1) over partial rows [row0, row0 + nrows) into out[0..):
-// one wave per slot, lanes stride the rows with four accumulators, a fixed
-// wave reduction -- a fixed order for every instance.
+// slots in batches of RQ; every thread adds rows t, t + blockDim, ... of each
+// slot of the batch (all loads of the batch in flight together), then a fixed
+// wave and cross-wave reduction -- a fixed order for every instance.
+constexpr int RQ = 8;
 __device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nrows, double *out) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int q = q0 + wave; q < q1; q += nw) {
-    const double *src = I.part + (size_t)q * I.prows + row0;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int t = lane;
-    for (; t + 192 < nrows; t += 256) {
-      s0 += src[t];
-      s1 += src[t + 64];
-      s2 += src[t + 128];
-      s3 += src[t + 192];
+  __shared__ double red[RBLOCK / 64][RQ];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int qb = q0; qb < q1; qb += RQ) {
+    const int nq = min(RQ, q1 - qb);
+    double s[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) s[u] = 0.0;
+    const double *src = I.part + (size_t)qb * I.prows + row0;
+    for (int t = tid; t < nrows; t += blockDim.x) {
+#pragma unroll
+      for (int u = 0; u < RQ; ++u)
+        if (u < nq) s[u] += src[(size_t)u * I.prows + t];
     }
-    for (; t < nrows; t += 64) s0 += src[t];
-    const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) out[q - q0] = s;
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const double v = wave_sum(s[u]);
+      if (lane == 0) red[wave][u] = v;
+    }
+    __syncthreads();
+    if (tid < nq) {
+      double v = 0.0;
+      for (int w = 0; w < nw; ++w) v += red[w][tid];
+      out[qb - q0 + tid] = v;
+    }
+    __syncthreads();
   }
   __syncthreads();
 }
@@ -947,17 +1152,19 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
   double *res = I.res->v;
   const int nt = I.ntiles;
   const int tid = threadIdx.x;
+  if (blockIdx.y > 0 && a.op != RD_LZ_H1 && a.op != RD_LZ_H2 && a.op != RD_GRAM) return;
   switch (a.op) {
     case RD_COMBO:
     case RD_NORM:
     case RD_TRIAL_PROJ: {
-      reduce_slots(I, 0, 1, 0, nt, S);
+      reduce_slots(I, 0, a.op == RD_TRIAL_PROJ ? 2 : 1, 0, nt, S);
       if (tid == 0) {
         if (a.op == RD_COMBO) res[S_XTW0] = S[0];
         else if (a.op == RD_NORM) res[S_NZ] = S[0];
         else {
           res[S_NZ] = S[0];
           res[S_PROJC] = S[0] > P.tau2 ? P.tau / sqrt(S[0]) : 1.0;
+          res[S_GR2T] = S[1];
         }
       }
       break;
@@ -991,7 +1198,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     }
     case RD_PROJ_DOTS:
     case RD_AIPP: {
-      reduce_slots(I, 0, 3, 0, nt, S);
+      reduce_slots(I, 0, a.op == RD_AIPP ? 4 : 3, 0, nt, S);
       if (tid == 0) {
         if (a.op == RD_PROJ_DOTS) {
           res[S_GR_D] = S[0];
@@ -1001,6 +1208,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
           res[S_RL2] = S[0];
           res[S_RL_W0] = S[1];
           res[S_WY] = S[2];
+          res[S_GR2A] = S[3];
         }
       }
       break;
@@ -1031,14 +1239,17 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     }
     case RD_LZ_H1:
     case RD_LZ_H2: {
+      // slots split over blockIdx.y in runs of RQ (independent coefficients)
       if (P.lz_steps <= 0) break;
       const int nq = P.lz_j + 1;
-      reduce_slots(I, 0, nq, 0, nt, S);
+      const int qa = blockIdx.y * RQ, qe = min(nq, qa + RQ);
+      if (qa >= nq) break;
+      reduce_slots(I, qa, qe, 0, nt, S);
       double *Hc = I.dl_base + P.dl_off + (size_t)(P.lz_j - P.lz_j0) * (KMAX + 2);
-      for (int q = tid; q < nq; q += blockDim.x) {
-        I.hcoef[q] = S[q];
-        if (a.op == RD_LZ_H1) Hc[q] = S[q];
-        else Hc[q] += S[q];
+      for (int q = qa + tid; q < qe; q += blockDim.x) {
+        I.hcoef[q] = S[q - qa];
+        if (a.op == RD_LZ_H1) Hc[q] = S[q - qa];
+        else Hc[q] += S[q - qa];
       }
       break;
     }
@@ -1059,9 +1270,11 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       break;
     }
     case RD_GRAM: {
+      // entries split over blockIdx.y in runs of 64
       const int R = a.R;
       const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-      for (int q = wave; q < R * R; q += nw) {
+      const int qe = min(R * R, (int)(blockIdx.y + 1) * 64);
+      for (int q = blockIdx.y * 64 + wave; q < qe; q += nw) {
         const double *src = I.gram + (size_t)q * nt;
         double s = 0.0;
         for (int t = lane; t < nt; t += 64) s += src[t];
@@ -1077,7 +1290,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
 
 // Lanczos start: V_0 = w / ||w||
 __global__ __launch_bounds__(BLOCK) void k_lz_first(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   double *V = lz_basis(I, P);
@@ -1322,7 +1535,10 @@ void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstD
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra) {
   if (ni <= 0) return;
   RedArgs a{op, zsel, R, extra};
-  hipLaunchKernelGGL(k_reduce, dim3(ni), dim3(RBLOCK), 0, s, ilist, d, a);
+  int ny = 1;
+  if (op == RD_LZ_H1 || op == RD_LZ_H2) ny = (KMAX + 1 + RQ - 1) / RQ;
+  else if (op == RD_GRAM) ny = (R * R + 63) / 64;
+  hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
 void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_start, dim3(nt), dim3(BLOCK), 0, s, t, d);

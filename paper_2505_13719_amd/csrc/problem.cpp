@@ -228,17 +228,24 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
   }
   hp.c_l1 = cl1;
   build_tiles(hp);
+  // the sparse kernels stage a tile's row pointers in LDS
+  for (const Tile &t : hp.tiles)
+    if (t.row1 - t.row0 > TILE_MAX_ROWS || t.row1 <= t.row0) {
+      *code = HALLAR_E_INVALID;
+      return "internal: tile row range outside the kernels' limits";
+    }
   *code = HALLAR_OK;
   return "";
 }
 
-// Tile schedule: contiguous row ranges closed at kTileWork units of work
-// (pairs + rows) or at the row target, with at most about kMaxTiles tiles
-// per instance, and per tile the number of pair streams per row (power of
-// two near the mean row length) for the SDDMM (upper rows) and the SpMM
-// (upper + lower rows).  Small instances get short tiles so that a launch
-// has many workgroups; the schedule depends on the instance only, so a
-// batched instance reduces in the same order as a standalone one.
+// Tile schedule: contiguous row ranges of at most TILE_MAX_ROWS rows and
+// TILE_MAX_ENTRIES entries of S u S^T (a row longer than that is a tile of its
+// own), aiming at about kMaxTiles tiles per large instance (8 workgroups per
+// CU) and at least kMinRows rows per tile for small ones.  Per tile, the
+// number of pair streams per row (power of two near the mean row length) is
+// kept for the kernels that walk rows with teams.  The schedule depends on
+// the instance only, so a batched instance reduces in the same order as a
+// standalone one.
 static int plog_for(double avg) {
   int pl = 0;
   while ((1 << pl) < avg && pl < 6) ++pl;
@@ -246,20 +253,20 @@ static int plog_for(double avg) {
 }
 
 void build_tiles(HostProblem &hp) {
-  constexpr int64_t kTileWork = 2048;
   constexpr int64_t kMaxTiles = 2048;
   constexpr int32_t kMinRows = 16;
   const int32_t n = hp.n;
-  const int64_t total = hp.npairs + hp.nlower + n;
-  const int64_t work_target = std::max<int64_t>(kTileWork, (total + kMaxTiles - 1) / kMaxTiles);
-  const int32_t row_target = std::max<int32_t>(kMinRows, (int32_t)((n + kMaxTiles - 1) / kMaxTiles));
+  const int32_t row_target =
+      std::min<int32_t>(TILE_MAX_ROWS, std::max<int32_t>(kMinRows, (int32_t)((n + kMaxTiles - 1) / kMaxTiles)));
   hp.tiles.clear();
   int32_t r0 = 0;
   while (r0 < n) {
-    int64_t work = 0;
+    int64_t ent = 0;
     int32_t r1 = r0;
-    while (r1 < n && (r1 - r0) < row_target && work < work_target) {
-      work += 1 + (hp.rowptr_u[r1 + 1] - hp.rowptr_u[r1]) + (hp.rowptr_l[r1 + 1] - hp.rowptr_l[r1]);
+    while (r1 < n && (r1 - r0) < row_target) {
+      const int64_t e = (hp.rowptr_u[r1 + 1] - hp.rowptr_u[r1]) + (hp.rowptr_l[r1 + 1] - hp.rowptr_l[r1]);
+      if (r1 > r0 && ent + e > TILE_MAX_ENTRIES) break;
+      ent += e;
       ++r1;
     }
     const double rows = (double)(r1 - r0);

@@ -1,7 +1,8 @@
 """Write tests/golden/refs.json: FP64 oracle solves of the seeded workloads
-the GPU solve tests compare against (eps = 1e-7, or 1e-6 where the oracle's
-iteration caps stop it before 1e-7).  Calls only oracle/ and the instance
-generators.  Usage: python tests/golden/make_refs.py [case ...]"""
+the GPU solve tests compare against (eps = 1e-7, or a looser eps where the
+oracle needs too long for 1e-7), with the a-posteriori objective bound
+|pval - dval| + |p^T (A(X) - b)| of each solve.  Calls only oracle/ and the
+instance generators.  Usage: python tests/golden/make_refs.py [case ...]"""
 import json
 import os
 import sys
@@ -24,7 +25,7 @@ def cases():
     yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}, 1e-6
     rng = np.random.default_rng(12)
     i, j = si.er_edges(150, 0.06, rng)
-    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-7
+    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-5
     yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}, 1e-7
 
 
@@ -36,8 +37,10 @@ def main(only):
             continue
         t = time.time()
         r = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=eps, time_limit=1800, **kw))
+        resid = oracle.a_tilde(prob, r.U)[1:] - prob.b
+        bound = abs(r.pval - r.dval) + abs(float(r.p @ resid))
         out[name] = dict(pval=r.pval, dval=r.dval, status=r.status, rank=r.rank, eps=eps, opts=kw,
-                         seconds=round(time.time() - t, 1))
+                         pinf=r.pinf, gap=r.gap, dinf=r.dinf, bound=bound, seconds=round(time.time() - t, 1))
         print(name, out[name], flush=True)
         with open(path, "w") as f:
             json.dump(out, f, indent=1, sort_keys=True)

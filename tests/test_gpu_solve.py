@@ -2,7 +2,7 @@
 
 Final objectives are compared with closed-form SDP values (Lovasz theta and
 MaxCut of vertex-transitive graphs) and with FP64 oracle solves at
-eps = 1e-7 (1e-6 for two cases) stored in tests/golden/refs.json (written by
+eps = 1e-7 (looser for two cases) stored in tests/golden/refs.json (written by
 make_refs.py, which calls only the oracle).  Bar: |pval - ref| <= 1e-5
 (1 + |ref|), with the solve's relative gap, infeasibility and dual
 infeasibility <= its eps.  The GPU solves for this bar run at eps = 1e-6:
@@ -100,14 +100,31 @@ def _make(name, maker):
     return si.theta_problem(150, i, j)
 
 
+def objective_bound(prob, res, U, p):
+    """|pval - dval| + |p^T (A(X) - b)|: with the dual iterate feasible up to
+    dinf, dval <= P* <= pval + |p^T r|, so this bounds |pval - P*|."""
+    import oracle
+    r = oracle.a_tilde(prob, U)[1:] - prob.b
+    return abs(res["pval"] - res["dval"]) + abs(float(p @ r))
+
+
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
 @pytest.mark.parametrize("name,maker,kw", REF_CASES, ids=[c[0] for c in REF_CASES])
 def test_against_oracle_reference(prec, name, maker, kw):
     if name not in REFS:
         pytest.skip("tests/golden/refs.json lacks " + name)
+    ref = REFS[name]
     prob = _make(name, maker)
-    res, _, _ = solve(prob, prec, eps=1e-6, **kw)
-    check(res, REFS[name]["pval"], 1e-6)
+    if ref["status"] == "ok" and ref["eps"] <= 1e-6:
+        res, _, _ = solve(prob, prec, eps=1e-6, **kw)
+        check(res, ref["pval"], 1e-6)
+    else:
+        # reference solved at a looser eps: both objectives lie within their
+        # a-posteriori bounds of the optimum
+        res, U, p = solve(prob, prec, eps=1e-5, **kw)
+        assert res["status"] == "ok", res
+        assert max(res["pinf"], res["gap"], res["dinf"]) <= 1e-5
+        assert abs(res["pval"] - ref["pval"]) <= objective_bound(prob, res, U, p) + ref["bound"] + 1e-9
 
 
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
