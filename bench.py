@@ -5,13 +5,17 @@ gap on one GPU, with the dominant kernel's achieved HBM bandwidth.
 One step is one complete HALLaR solve (operators, ADAP-FISTA/ADAP-AIPP,
 Lanczos, Frank-Wolfe, multiplier updates, relative termination) of a seeded
 synthetic instance resident in HBM.  Workloads (--workload):
+  mc      matrix completion, 1e5 x 1e5 rank 3, m = 1.2e7, FP32-mixed,
+          rank cap 16 (default)
   torus   MaxCut SDP, 1000 x 1000 torus (n = 1e6), +-1 weights, FP32-mixed,
-          rank cap 32 (default)
+          rank cap 32 (does not reach 1e-5 within the limits: its solution
+          rank grows with n far beyond 32)
   er800   MaxCut SDP, G(800, 0.02), unit weights, FP64, rank cap 16
   theta   Lovasz theta SDP, G(5e4, avg deg 10), FP32-mixed, rank cap 64
-  mc      matrix completion, 1e5 x 1e5 rank 3, m = 1.2e7, FP32-mixed
   served  stream of MaxCut requests (n log-uniform in [100, 2e4], deg 8,
           +-1 weights) through the continuous-batching pool; reports p50/p99
+  ops     operator-level timing (SDDMM and SpMM entry points, --ops-instance
+          mc or torus) with a 1 GiB copy for HBM counter calibration
 Prints one JSON line.
 """
 import argparse
@@ -231,15 +235,60 @@ def bench_served(args):
     return out
 
 
+def bench_ops(args):
+    """Operator-level timing on the instance of --ops-instance (FP32-mixed;
+    r = 4 for matrix completion, 32 for the torus): hallar_eval_AUUt (SDDMM +
+    AL epilogue) and hallar_adjoint_spmm (SpMM), each called --steps times on a
+    random U, plus a plain 1 GiB device copy (the calibration kernel for the
+    HBM byte counters)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_13719_amd import hallar as H
+
+    prob, prec, kw, cfg = workload(args.ops_instance)
+    dev = torch.device("cuda:0")
+    r = 4 if args.ops_instance == "mc" else 32
+    h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, **kw))
+    g = torch.Generator(device="cpu").manual_seed(0)
+    U = (torch.randn((prob.n, r), generator=g, dtype=torch.float32) / math.sqrt(r)).to(dev)
+    W = torch.empty_like(U)
+    T = torch.empty(prob.m + 1, dtype=torch.float64, device=dev)
+    p = torch.tensor(np.random.default_rng(1).standard_normal(prob.m), device=dev)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        H.hallar_eval_AUUt(h, U, T)
+        H.hallar_adjoint_spmm(h, p, U, W)
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("eval_AUUt", lambda: H.hallar_eval_AUUt(h, U, T)),
+                     ("adjoint_spmm", lambda: H.hallar_adjoint_spmm(h, p, U, W)),
+                     ("copy_1GiB", lambda: dst.copy_(src))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1) * 1e3 / args.steps, 2)
+        print(f"[bench] {name}: {out[name]} us/call", file=sys.stderr, flush=True)
+    H.hallar_destroy(h)
+    return {"metric": "operator us/call", "config": dict(cfg, r=r), "us_per_call": out,
+            "copy_gbs": round(2 * (1 << 30) / (out["copy_1GiB"] * 1e-6) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="torus", choices=["torus", "er800", "theta", "mc", "served"])
+    ap.add_argument("--workload", default="mc", choices=["torus", "er800", "theta", "mc", "served", "ops"])
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0, help="solver progress on stderr (1: outer, 2: HLR)")
+    ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--served-requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")
@@ -250,7 +299,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
-    out = bench_served(args) if args.workload == "served" else bench_solve(args)
+    if args.workload == "ops":
+        out = bench_ops(args)
+    else:
+        out = bench_served(args) if args.workload == "served" else bench_solve(args)
     print(json.dumps(out))
 
 

@@ -88,6 +88,7 @@ typedef struct {
 typedef struct {
   double eps;            /* relative tolerance of eq. termination2 (default 1e-5) */
   double beta1, beta_growth, beta_max, infeas_ratio, pinf_gate;
+  double stall_ratio, stall_growth; /* ||r_t|| > stall_ratio ||r_{t-1}||: grow beta by stall_growth */
   double eps1, eps_floor, eps_decay;
   double sigma, chi, lam0;          /* ADAP-AIPP / ADAP-FISTA universal parameters */
   int32_t fista_max_iter, aipp_max_iter, hlr_max_iter, outer_max_iter;

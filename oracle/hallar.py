@@ -66,6 +66,8 @@ class Options:
     beta_rule: str = "ratio"
     infeas_ratio: float = 0.5
     pinf_gate: float = 0.1
+    stall_ratio: float = 0.9        # ||r_t|| above this fraction of ||r_{t-1}||: growth stall_growth
+    stall_growth: float = 16.0
     balance: float = 3.0
     rho_over_tau: bool = True
     beta_min: float = 1e-3
@@ -363,7 +365,8 @@ def hallar(prob, U0, opts: Options = None, p0=None):
             # LANCELOT-like: raise the penalty when the infeasibility did not
             # drop by the factor infeas_ratio since the previous outer iteration
             if rnorm > opts.infeas_ratio * rnorm_prev and pinf > opts.pinf_gate * max(gap, dinf):
-                beta = min(beta * opts.beta_growth, opts.beta_max)
+                grow = opts.stall_growth if rnorm > opts.stall_ratio * rnorm_prev else opts.beta_growth
+                beta = min(beta * grow, opts.beta_max)
         else:
             if pinf > opts.balance * max(gap, dinf):
                 beta = min(beta * opts.beta_growth, opts.beta_max)

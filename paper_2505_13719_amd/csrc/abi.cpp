@@ -34,7 +34,10 @@ hallar_status failp(hallar_pool_t p, hallar_status st, const std::string &msg) {
 
 bool check_opts(const hallar_options &o, std::string &msg) {
   if (!(o.eps > 0)) { msg = "opts.eps must be > 0"; return false; }
-  if (!(o.beta1 > 0) || !(o.beta_growth >= 1.0)) { msg = "opts.beta1 > 0 and beta_growth >= 1 required"; return false; }
+  if (!(o.beta1 > 0) || !(o.beta_growth >= 1.0) || !(o.stall_growth >= 1.0)) {
+    msg = "opts.beta1 > 0, beta_growth >= 1 and stall_growth >= 1 required";
+    return false;
+  }
   if (!(o.sigma > 0 && o.sigma < 0.5) || !(o.chi > 0 && o.chi < 1)) { msg = "opts.sigma in (0, 1/2), chi in (0, 1) required"; return false; }
   if (!(o.lam0 > 0)) { msg = "opts.lam0 must be > 0"; return false; }
   if (o.rank_cap < 0 || o.rank_cap > hl::R_MAX) { msg = "opts.rank_cap must be in [0, 64]"; return false; }
@@ -66,6 +69,8 @@ void hallar_default_options(hallar_options *o) {
   o->beta_max = 1e8;
   o->infeas_ratio = 0.5;
   o->pinf_gate = 0.1;
+  o->stall_ratio = 0.9;
+  o->stall_growth = 16.0;
   o->eps1 = 1e-2;
   o->eps_floor = 0.2;
   o->eps_decay = 0.5;

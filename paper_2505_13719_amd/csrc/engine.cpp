@@ -570,11 +570,13 @@ static void launch_group(Pool &P, const Group &g) {
     case OP_LZ_STEPS:
       // instances with fewer steps skip the extra ones (their lz_steps counter reaches 0)
       for (int k = 0; k < g.steps; ++k) {
-        double vb = 0;  // basis bytes of this step's two dots + two updates
+        // algorithmic bytes of one Gram-Schmidt pass (dots + update over the
+        // basis and w); a second pass, when the device runs it, is overhead
+        double vb = 0;
         if (P.profile)
           for (int s : g.slots) {
             const Slot &S = *P.slots[s];
-            if (k < S.prm.lz_steps) vb += 4.0 * (S.prm.lz_j + k + 1) * S.hp.n * 8 + 8.0 * S.hp.n * 8;
+            if (k < S.prm.lz_steps) vb += 2.0 * (S.prm.lz_j + k + 1) * S.hp.n * 8 + 3.0 * S.hp.n * 8;
           }
         {
           ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv);
@@ -582,10 +584,14 @@ static void launch_group(Pool &P, const Group &g) {
         }
         {
           ProfScope ps(P, KC_LZ_ORTH, vb);
-          op_lz_dots(st, T, nt, D);
+          // classical Gram-Schmidt against the whole basis; the second pass
+          // runs only where the first removed most of w (the device decides
+          // per instance, the skipped kernels return at once)
+          op_lz_dots(st, T, nt, D, 0);
           op_reduce(st, IL, ni, D, RDH_LZ_H1, 0, R, 0);
           op_lz_update(st, T, nt, D, 0);
-          op_lz_dots(st, T, nt, D);
+          op_reduce(st, IL, ni, D, RDH_LZ_CHECK, 0, R, 0);
+          op_lz_dots(st, T, nt, D, 1);
           op_reduce(st, IL, ni, D, RDH_LZ_H2, 0, R, 0);
           op_lz_update(st, T, nt, D, 1);
           op_reduce(st, IL, ni, D, RDH_LZ_FINAL, 0, R, 0);
@@ -801,16 +807,20 @@ struct Ctx {
 static bool finite(double x) { return std::isfinite(x); }
 
 struct FistaOut {
-  int status = 0;  // 0 ok, 1 fail, 2 numerical
+  int status = 0;  // 0 ok, 1 fail, 2 numerical, 3 no representable progress
   int W = -1;
   double L = 0, gW = 0, rl2 = 0, vdot = 0, dW2 = 0, wy = 0, gr2 = 0;
 };
 
 // Unit roundoff of the storage type of U and of the gradient buffer.  Function
-// values are exact for the stored iterates (products accumulate in FP64), but
-// the stored gradient GR is rounded to this precision, so an inner product
-// <GR, d> carries an error of at most u ||GR|| ||d||; the tests below allow
-// for it (negligible in FP64).
+// values and products are exact (FP64 accumulation) for the stored iterates,
+// but (i) the stored gradient GR is rounded, so <GR, d> errs by up to
+// u ||GR|| ||d||, and (ii) every new iterate is rounded on store, which moves
+// it by up to u tau (||U|| <= tau) and psi by up to (||grad psi|| + L ||d||) u tau.
+// The FISTA / AIPP inequalities below allow for these terms, and ADAP-AIPP's
+// residual is resolved only down to u (||GR|| + L tau) / lam.  In FP64 all of
+// them are below the 1e-13 relative slack; in FP32-mixed they keep rounding
+// noise from reading as a failed descent (which would halve lam without end).
 static double storage_eps(int prec) { return prec == 0 ? 0x1p-53 : 0x1p-24; }
 
 // ADAP-FISTA (Appendix A.1) on psi_s = lam g + 1/2 ||. - x0||^2 over B_tau.
@@ -866,7 +876,8 @@ static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
         goto cleanup;
       }
       const double psx = lam * g_xt + 0.5 * xtw0, psy = lam * g_yp + 0.5 * ypw0;
-      const double slack = 4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(c.res(S_GR2T), 0.0) * std::max(d2, 0.0));
+      const double grn = std::sqrt(std::max(c.res(S_GR2T), 0.0)), dn = std::sqrt(std::max(d2, 0.0));
+      const double slack = 4.0 * storage_eps(c.P.prec) * ((grn + L * dn) * c.S.prm.tau + grn * dn);
       if (psx + gr_d + 0.25 * (1.0 - chi) * L * d2 >= psy - slack) {
         accepted = true;
         break;
@@ -883,7 +894,9 @@ static Task fista(Ctx c, int x0, double lam, double L0, FistaOut &out) {
       u2 = tk / tk1;
       u3 = -a * (L - mu) / tk1;
       if (ypw0 < chi * A1 * L * d2) {
-        out.status = 1;
+        // y+ equal to x0 up to the storage rounding: no representable step
+        const double ut = 4.0 * storage_eps(c.P.prec) * c.S.prm.tau;
+        out.status = ypw0 <= ut * ut ? 3 : 1;
         goto cleanup;
       }
       if ((L - mu) * std::sqrt(d2) <= sigma * std::sqrt(ypw0)) {
@@ -951,10 +964,20 @@ static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out)
         out.W = Wprev;
         co_return;
       }
+      if (fo.status == 3) {
+        // the prox step no longer moves the stored iterate: W_{j-1} is
+        // stationary to the storage precision
+        out.status = 0;
+        out.W = Wprev;
+        out.lam = lam;
+        out.g = gprev;
+        co_return;
+      }
       if (fo.status == 0) {
         const double lhs = lam * gprev - (lam * fo.gW + 0.5 * fo.dW2);
+        const double grn = std::sqrt(std::max(fo.gr2, 0.0)), dn = std::sqrt(std::max(fo.dW2, 0.0));
         const double slack = 1e-13 * (1.0 + std::fabs(lam * gprev)) +
-                             4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(fo.gr2, 0.0) * std::max(fo.dW2, 0.0));
+                             4.0 * storage_eps(c.P.prec) * ((grn + dn) * c.S.prm.tau + grn * dn);
         if (lhs >= fo.vdot - slack) break;
         c.release(fo.W);
       }
@@ -967,7 +990,7 @@ static Task aipp(Ctx c, int W0, double g0, double lam, double rho, AippOut &out)
     }
     const double Rn = std::sqrt(std::max(fo.rl2, 0.0)) / lam;
     // R_j is resolved only down to the rounding of the stored gradient
-    const double Rfloor = 4.0 * storage_eps(c.P.prec) * std::sqrt(std::max(fo.gr2, 0.0)) / lam;
+    const double Rfloor = 4.0 * storage_eps(c.P.prec) * (std::sqrt(std::max(fo.gr2, 0.0)) + fo.L * c.S.prm.tau) / lam;
     Mbar = fo.L;
     c.release(Wprev);
     Wprev = fo.W;
@@ -1312,7 +1335,7 @@ static Task solve_main(Ctx c) {
       break;
     }
     if (rnorm > o.infeas_ratio * rnorm_prev && pinf > o.pinf_gate * std::max(gapr, dinf))
-      beta = std::min(beta * o.beta_growth, o.beta_max);
+      beta = std::min(beta * (rnorm > o.stall_ratio * rnorm_prev ? o.stall_growth : o.beta_growth), o.beta_max);
     S.prm.beta = beta;
     rnorm_prev = rnorm;
     pval_prev = pval;

@@ -20,6 +20,7 @@ constexpr int LR_MAX = 2;        // rank of the low-rank objective term
 constexpr int R_MAX = 64;        // columns of U
 constexpr int KMAX = 64;         // Lanczos basis vectors before a restart
 constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR_MAX, >= 3 + LR_MAX * R_MAX)
+constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos SpMV
 constexpr int NRES = 32;         // result scalars per instance
 constexpr int TILE_MAX_ROWS = 1024;     // rows of a tile (row pointers staged in LDS)
 constexpr int TILE_MAX_ENTRIES = 2048;  // entries of S u S^T staged per tile (longer tiles: single rows)
@@ -60,6 +61,7 @@ struct InstParams {
   int32_t rnew;         // columns after a rotation
   int32_t lz_j0;        // lz_j at the start of the round (download layout)
   int32_t lz_use_prev;  // Lanczos start: previous vector + small noise
+  int32_t lz_skip;      // set on the device: this step's second Gram-Schmidt pass is not needed
   int32_t fw_v_on;      // Frank-Wolfe direction present (theta > 0)
   uint64_t lz_seed;     // counter-based start-vector seed
   int64_t up_off;       // offset of this instance's coefficients in the upload buffer
@@ -80,6 +82,7 @@ enum ResSlot : int {
   S_YT,                 // sum_l y'_l T_l (G . XX^T = T_0 + sum_l y'_l T_l)
   S_GR2T,               // ||GR||^2 of a FISTA trial (rounding bound of <GR, d>)
   S_GR2A,               // ||GR||^2 at ADAP-FISTA's output (rounding bound of R_j)
+  S_LZ_W2,              // ||G v_j||^2 before reorthogonalisation (second-pass test)
   S_COUNT
 };
 

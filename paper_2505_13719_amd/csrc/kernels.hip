@@ -49,7 +49,7 @@ __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); 
 
 // Block reduction of NQ doubles per thread into partial row `row` of the
 // instance (slot q at part[q * prows + row]).
-template <int NQ>
+template <int NQ, int BASE = 0>
 __device__ __forceinline__ void block_partials(double (&acc)[NQ], const InstDev &I, int row) {
   __shared__ double red[BLOCK / 64][NQ > 0 ? NQ : 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -63,7 +63,7 @@ __device__ __forceinline__ void block_partials(double (&acc)[NQ], const InstDev 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) s += red[w][threadIdx.x];
-    I.part[(size_t)threadIdx.x * I.prows + row] = s;
+    I.part[(size_t)(BASE + threadIdx.x) * I.prows + row] = s;
   }
 }
 
@@ -98,21 +98,126 @@ struct SddmmArgs {
   int32_t write_yp;  // store y'_l in yp
 };
 
+// Narrow rows (at most two 16-byte chunks): one thread per pair holds both
+// rows, all of a pair's loads are independent, no LDS round trip beyond the
+// tile's row pointers; two pairs per thread in flight.
+template <typename T, int G>
+__device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                             const SddmmArgs &a) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int NQ = 4;
+  constexpr int UP = 2;
+  __shared__ int32_t s_rp[TILE_MAX_ROWS + 1];
+  const Tile tl = tiles[tile_index()];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
+  const T *__restrict__ cu = reinterpret_cast<const T *>(I.c_u);
+  const T *__restrict__ pa = reinterpret_cast<const T *>(I.pa);
+  T *mout = a.msel == 0 ? reinterpret_cast<T *>(I.m_xt) : (a.msel == 1 ? reinterpret_cast<T *>(I.m_yp) : nullptr);
+  const double beta = P.beta;
+  const int direct = I.direct;
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) s_rp[r] = I.rowptr_u[tl.row0 + r];
+  __syncthreads();
+  const int kbeg = s_rp[0], kend = s_rp[nrows];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int kb = kbeg + threadIdx.x; kb < kend; kb += BLOCK * UP) {
+    int kk[UP], ii[UP], jj[UP], l[UP];
+    double cv[UP], av[UP], bl[UP], pl[UP];
+    Chunk<T> ci[UP][G], cj[UP][G];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      const int k = kb + u * BLOCK;
+      kk[u] = k;
+      l[u] = 0;
+      cv[u] = av[u] = bl[u] = pl[u] = 0.0;
+      ii[u] = jj[u] = 0;
+      if (k < kend) {
+        int lo = 0, hi = nrows - 1;  // last row whose first pair is <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rp[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        ii[u] = tl.row0 + lo;
+        jj[u] = I.col_u[k];
+        cv[u] = cu ? (double)cu[k] : 0.0;
+        if (direct) {
+          l[u] = I.pcon[k];
+          if (l[u] > 0) {
+            av[u] = (double)pa[k];
+            bl[u] = I.b[l[u] - 1];
+            pl[u] = I.p[l[u] - 1];
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        ci[u][c] = ldc(X + (size_t)ii[u] * R + c * NC);
+        cj[u][c] = ldc(X + (size_t)jj[u] * R + c * NC);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+      const int k = kk[u];
+      if (k >= kend) continue;
+      // FP64 accumulation of the FP32 / FP64 products
+      double B = 0.0;
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int e = 0; e < NC; ++e) B += (double)ci[u][c].v[e] * (double)cj[u][c].v[e];
+      const double w2 = ii[u] == jj[u] ? 1.0 : 2.0;
+      acc[0] += w2 * cv[u] * B;
+      if (direct) {
+        double mv = cv[u];
+        if (l[u] > 0) {
+          const double t = w2 * av[u] * B;
+          const double r = t - bl[u];
+          const double y = pl[u] + beta * r;
+          acc[1] += pl[u] * r;
+          acc[2] += r * r;
+          acc[3] += y * t;
+          if (a.write_T) I.TY[l[u] - 1] = t;
+          if (a.write_yp) I.yp[l[u] - 1] = y;
+          mv = cv[u] + av[u] * y;
+        }
+        if (mout) mout[k] = (T)mv;
+      } else {
+        I.Bpair[k] = B;
+      }
+    }
+  }
+  block_partials<NQ>(acc, I, tl.lt);
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                  SddmmArgs a) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
   constexpr int NQ = 4;          // T0, p^T r, ||r||^2, sum y' T
-  constexpr int PPP = BLOCK / G;  // pairs per pass (one G-lane group per pair)
-  constexpr int UN = G < 4 ? G : 4;
-  // The tile's pairs are taken in batches of BLOCK: (A) one thread per pair
-  // loads its row (search in the tile's row pointers), column and epilogue
-  // operands; (B) G-lane groups form the dot products, UN pairs per group in
-  // flight; (C) one thread per pair applies the epilogue.
+  if constexpr (G <= 2) {
+    sddmm_narrow<T, G>(tiles, insts, a);
+    return;
+  }
+  constexpr int PPP = BLOCK / G;           // pairs per pass (one G-lane group per pair)
+  constexpr int PPT = G >= 4 ? 1 : 4 / G;  // pairs per thread in phases A and C
+  constexpr int BB = BLOCK * PPT;          // pairs per batch
+  constexpr int NP = BB / PPP;             // passes per batch (= G * PPT)
+  constexpr int UN = NP < 4 ? NP : 4;
+  // The tile's pairs are taken in batches of BB: (A) one thread per pair
+  // (PPT pairs each) loads its row (search in the tile's row pointers),
+  // column and epilogue operands; (B) G-lane groups form the dot products,
+  // UN pairs per group in flight; (C) one thread per pair applies the
+  // epilogue.
   __shared__ int32_t s_rp[TILE_MAX_ROWS + 1];
-  __shared__ int32_t s_i[BLOCK], s_j[BLOCK];
-  __shared__ double s_d[BLOCK];
+  __shared__ int32_t s_i[BB], s_j[BB];
+  __shared__ double s_d[BB];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
@@ -131,33 +236,37 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
-  for (int kb = kbeg; kb < kend; kb += BLOCK) {
-    const int k = kb + threadIdx.x;
-    const bool valid = k < kend;
-    int l = 0;
-    double cv = 0.0, av = 0.0, bl = 0.0, pl = 0.0;
-    if (valid) {
-      int lo = 0, hi = nrows - 1;  // last row whose first pair is <= k
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_rp[mid] <= k) lo = mid;
-        else hi = mid - 1;
-      }
-      s_i[threadIdx.x] = tl.row0 + lo;
-      s_j[threadIdx.x] = I.col_u[k];
-      cv = cu ? (double)cu[k] : 0.0;
-      if (direct) {
-        l = I.pcon[k];
-        if (l > 0) {
-          av = (double)pa[k];
-          bl = I.b[l - 1];
-          pl = I.p[l - 1];
+  for (int kb = kbeg; kb < kend; kb += BB) {
+    int l[PPT];
+    double cv[PPT], av[PPT], bl[PPT], pl[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int pb = threadIdx.x + u * BLOCK, k = kb + pb;
+      l[u] = 0;
+      cv[u] = av[u] = bl[u] = pl[u] = 0.0;
+      if (k < kend) {
+        int lo = 0, hi = nrows - 1;  // last row whose first pair is <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rp[mid] <= k) lo = mid;
+          else hi = mid - 1;
+        }
+        s_i[pb] = tl.row0 + lo;
+        s_j[pb] = I.col_u[k];
+        cv[u] = cu ? (double)cu[k] : 0.0;
+        if (direct) {
+          l[u] = I.pcon[k];
+          if (l[u] > 0) {
+            av[u] = (double)pa[k];
+            bl[u] = I.b[l[u] - 1];
+            pl[u] = I.p[l[u] - 1];
+          }
         }
       }
     }
     __syncthreads();
-    const int nb = min(BLOCK, kend - kb);
-    for (int ps = 0; ps < G; ps += UN) {
+    const int nb = min(BB, kend - kb);
+    for (int ps = 0; ps < NP; ps += UN) {
       Chunk<T> ci[UN], cj[UN];
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
@@ -183,22 +292,25 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
       }
     }
     __syncthreads();
-    if (valid) {
-      const double B = s_d[threadIdx.x];
-      const double w2 = (s_i[threadIdx.x] == s_j[threadIdx.x]) ? 1.0 : 2.0;
-      acc[0] += w2 * cv * B;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int pb = threadIdx.x + u * BLOCK, k = kb + pb;
+      if (k >= kend) continue;
+      const double B = s_d[pb];
+      const double w2 = (s_i[pb] == s_j[pb]) ? 1.0 : 2.0;
+      acc[0] += w2 * cv[u] * B;
       if (direct) {
-        double mv = cv;
-        if (l > 0) {
-          const double t = w2 * av * B;
-          const double r = t - bl;
-          const double y = pl + beta * r;
-          acc[1] += pl * r;
+        double mv = cv[u];
+        if (l[u] > 0) {
+          const double t = w2 * av[u] * B;
+          const double r = t - bl[u];
+          const double y = pl[u] + beta * r;
+          acc[1] += pl[u] * r;
           acc[2] += r * r;
           acc[3] += y * t;
-          if (a.write_T) I.TY[l - 1] = t;
-          if (a.write_yp) I.yp[l - 1] = y;
-          mv = cv + av * y;
+          if (a.write_T) I.TY[l[u] - 1] = t;
+          if (a.write_yp) I.yp[l[u] - 1] = y;
+          mv = cv[u] + av[u] * y;
         }
         if (mout) mout[k] = (T)mv;
       } else {
@@ -422,8 +534,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
   constexpr int NQ = MODE == SP_AIPP ? 4 : (MODE == SP_TRIAL ? 2 : 1);
-  constexpr int RPP = BLOCK / G;  // rows per pass (one G-lane group per row)
-  constexpr int UN = 8;           // gathers in flight per lane
+  constexpr int UN = 8;  // gathers in flight per lane
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   __shared__ int32_t s_col[TILE_MAX_ENTRIES];
   __shared__ T s_m[TILE_MAX_ENTRIES];
@@ -456,12 +567,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
       s_m[nu + e] = m[I.pid_l[kl0 + e]];
     }
     __syncthreads();
-    const int ch = threadIdx.x % G, grp = threadIdx.x / G;
-    for (int rb = 0; rb < nrows; rb += RPP) {
-      const int r = rb + grp;
+    // a team of G * S lanes per row: S pair streams (power of two) when the
+    // tile has fewer rows than the block has G-lane groups (long rows)
+    int S = 1;
+    while (S * 2 * G <= 64 && nrows * S * 2 * G <= BLOCK) S *= 2;
+    const int TS = G * S;
+    const int team = threadIdx.x / TS, lt = threadIdx.x - team * TS;
+    const int strm = lt / G, ch = lt - strm * G;
+    const int nteams = BLOCK / TS;
+    for (int rb = 0; rb < nrows; rb += nteams) {
+      const int r = rb + team;
       if (r >= nrows) continue;
       const int i = tl.row0 + r;
-      const EpiIn<T> in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
+      EpiIn<T> in;
+      if (strm == 0) in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
       const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
       const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
       // FP64 accumulation (also for FP32 data): near a stationary point the
@@ -470,7 +589,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
       double w[NC];
 #pragma unroll
       for (int e = 0; e < NC; ++e) w[e] = 0.0;
-      for (int q = 0; q < cnt; q += UN) {
+      for (int q = strm * UN; q < cnt; q += S * UN) {
         Chunk<T> x[UN];
         double mv[UN];
 #pragma unroll
@@ -491,7 +610,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
 #pragma unroll
           for (int e = 0; e < NC; ++e) w[e] += mv[u] * (double)x[u].v[e];
       }
-      spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
+      for (int o = TS / 2; o >= G; o >>= 1) {
+#pragma unroll
+        for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
+      }
+      if (strm == 0) spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
     }
   } else {
     // a tile too long to stage (one row of very high degree): teams of
@@ -891,6 +1014,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tile
   const int team = threadIdx.x >> plog;
   const int strm = threadIdx.x & (TS - 1);
   const int nteams = BLOCK >> plog;
+  double acc[1] = {0.0};
   for (int r = team; r < nrows; r += nteams) {
     const int i = tl.row0 + r;
     double w = 0.0;
@@ -923,17 +1047,20 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tile
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
       I.w[i] = w;
+      acc[0] += w * w;
     }
   }
+  if (!from_lzv) block_partials<1, LZ_W2_SLOT>(acc, I, tl.lt);
 }
 
 // partial dots: q < nq: <V_q, w>; if lr: K0^T w at slots nq.. (only for the final pass)
-__global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+__global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                   int32_t second_pass) {
   __shared__ double lds[(BLOCK / 64) * PSTRIDE];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
-  if (P.lz_steps <= 0) return;
+  if (P.lz_steps <= 0 || (second_pass && P.lz_skip)) return;
   const double *V = lz_basis(I, P);
   const int nq = P.lz_j + 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -960,13 +1087,14 @@ __global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tile
   for (int q = threadIdx.x; q < nq; q += BLOCK) I.part[(size_t)q * I.prows + tl.lt] = lds[q];
 }
 
-// w -= sum_q V_q h_q; in the final pass also partial ||w||^2 and K0^T w.
+// w -= sum_q V_q h_q, partial ||w||^2 and K0^T w (both passes: after the
+// first they decide whether the second is needed).
 __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                      int32_t final_pass) {
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
-  if (P.lz_steps <= 0) return;
+  if (P.lz_steps <= 0 || (final_pass && P.lz_skip)) return;
   const double *V = lz_basis(I, P);
   const int nq = P.lz_j + 1;
   const size_t n = I.n;
@@ -978,12 +1106,10 @@ __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ ti
     double wi = I.w[i];
     for (int q = 0; q < nq; ++q) wi -= V[(size_t)q * n + i] * h[q];
     I.w[i] = wi;
-    if (final_pass) {
-      acc[0] += wi * wi;
-      for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
-    }
+    acc[0] += wi * wi;
+    for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
   }
-  if (final_pass) block_partials<1 + LR_MAX>(acc, I, tl.lt);
+  block_partials<1 + LR_MAX>(acc, I, tl.lt);
 }
 
 // v_{j+1} = w / beta_j (beta from the reduce kernel)
@@ -1076,7 +1202,8 @@ enum RedOp : int {
   RD_SETP,         // b^T p, ||r||^2 (constraint-major partials)
   RD_NORM,         // ||.||^2 of a pack / copy
   RD_GEN_EXTRA,    // general mode: add constraint-major p^T r, ||r||^2 rows
-  RD_GRAM          // sum gram partials
+  RD_GRAM,         // sum gram partials
+  RD_LZ_CHECK      // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2)
 };
 
 struct RedArgs {
@@ -1219,9 +1346,20 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       break;
     }
     case RD_LZ_START:
+    case RD_LZ_CHECK:
     case RD_LZ_FINAL: {
-      if (a.op == RD_LZ_FINAL && P.lz_steps <= 0) break;
+      // (P.lz_skip and P.lz_steps are read by every thread before the
+      // barriers in reduce_slots; thread 0 writes them after)
+      if (a.op != RD_LZ_START && P.lz_steps <= 0) break;
+      if (a.op == RD_LZ_FINAL && P.lz_skip) break;  // done by RD_LZ_CHECK
       reduce_slots(I, 0, 1 + I.r0, 0, nt, S);
+      if (a.op == RD_LZ_CHECK) {
+        // DGKS criterion: one classical Gram-Schmidt pass suffices unless it
+        // removed most of w (cancellation), eta = 1 / sqrt(2)
+        const bool skip = 2.0 * S[0] >= res[S_LZ_W2];
+        if (tid == 0) P.lz_skip = skip ? 1 : 0;
+        if (!skip) break;
+      }
       if (tid == 0) {
         const double b = sqrt(S[0]);
         res[S_LZ_BETA] = b;
@@ -1240,8 +1378,12 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     case RD_LZ_H1:
     case RD_LZ_H2: {
       // slots split over blockIdx.y in runs of RQ (independent coefficients)
-      if (P.lz_steps <= 0) break;
+      if (P.lz_steps <= 0 || (a.op == RD_LZ_H2 && P.lz_skip)) break;
       const int nq = P.lz_j + 1;
+      if (a.op == RD_LZ_H1 && blockIdx.y == 0) {
+        reduce_slots(I, LZ_W2_SLOT, LZ_W2_SLOT + 1, 0, nt, E);
+        if (tid == 0) res[S_LZ_W2] = E[0];
+      }
       const int qa = blockIdx.y * RQ, qe = min(nq, qa + RQ);
       if (qa >= nq) break;
       reduce_slots(I, qa, qe, 0, nt, S);
@@ -1549,8 +1691,8 @@ void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
 void op_lz_spmv(hipStream_t s, const Tile *t, int nt, const InstDev *d, int from_lzv) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_spmv, dim3(nt), dim3(BLOCK), 0, s, t, d, from_lzv);
 }
-void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  if (nt > 0) hipLaunchKernelGGL(k_lz_dots, dim3(nt), dim3(BLOCK), 0, s, t, d);
+void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d, int second_pass) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_dots, dim3(nt), dim3(BLOCK), 0, s, t, d, second_pass);
 }
 void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int final_pass) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_update, dim3(nt), dim3(BLOCK), 0, s, t, d, final_pass);

@@ -34,7 +34,8 @@ class hallar_problem(C.Structure):
 
 class hallar_options(C.Structure):
     _fields_ = [("eps", C.c_double), ("beta1", C.c_double), ("beta_growth", C.c_double), ("beta_max", C.c_double),
-                ("infeas_ratio", C.c_double), ("pinf_gate", C.c_double), ("eps1", C.c_double),
+                ("infeas_ratio", C.c_double), ("pinf_gate", C.c_double), ("stall_ratio", C.c_double),
+                ("stall_growth", C.c_double), ("eps1", C.c_double),
                 ("eps_floor", C.c_double), ("eps_decay", C.c_double), ("sigma", C.c_double), ("chi", C.c_double),
                 ("lam0", C.c_double), ("fista_max_iter", C.c_int32), ("aipp_max_iter", C.c_int32),
                 ("hlr_max_iter", C.c_int32), ("outer_max_iter", C.c_int32), ("eig_tol", C.c_double),

@@ -25,7 +25,7 @@ def cases():
     yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}, 1e-6
     rng = np.random.default_rng(12)
     i, j = si.er_edges(150, 0.06, rng)
-    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-5
+    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-7
     yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}, 1e-7
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_match_oracle_readings():
     o = H.options()
     ref = oracle.Options()
-    for k in ("eps", "beta1", "beta_growth", "beta_max", "infeas_ratio", "pinf_gate", "eps1", "eps_floor",
+    for k in ("eps", "beta1", "beta_growth", "beta_max", "infeas_ratio", "pinf_gate", "stall_ratio", "stall_growth", "eps1", "eps_floor",
               "eps_decay", "sigma", "chi", "lam0", "drop_tol", "eig_frac"):
         assert getattr(o, k) == pytest.approx(getattr(ref, k)), k
 
