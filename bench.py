@@ -50,6 +50,33 @@ def workload(name):
     raise ValueError(name)
 
 
+PROFILE_TAG = {"mc": "mc_1e5x1e5_r3", "torus": "torus_1000x1000_pm1", "er800": "maxcut_er800",
+               "theta": "theta_er50000", "served": "served_maxcut"}
+CLASS_KERNEL = {"sddmm": "k_sddmm<", "spmm": "k_spmm<", "lanczos_spmv": "k_lz_spmv"}
+
+
+def counted_traffic(workload_name, cls):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (two rocprofv3 --pmc passes, calibrated on a 1 GiB copy), or None
+    when there is none or the kernels changed since it was taken."""
+    import hashlib
+    tag = PROFILE_TAG.get(workload_name)
+    if tag is None or cls not in CLASS_KERNEL:
+        return None
+    path = os.path.join(ROOT, "profiles", tag + "_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = os.path.join(ROOT, "paper_2505_13719_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if "kernels.hip sha256[:16] = " + sha not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch[") and CLASS_KERNEL[cls] in line:
+            return float(line.split("=")[-1])
+    return None
+
+
 def roofline_from_profile(prof):
     """Dominant kernel class by time among the memory-streaming classes."""
     cands = {k: v for k, v in prof.items() if v["bytes"] > 0 and v["ms"] > 0}
@@ -144,6 +171,8 @@ def bench_solve(args):
     prof = H.hallar_profile(h)
     H.hallar_destroy(h)
     roof, table = roofline_from_profile(prof)
+    if roof:
+        roof["traffic"] = counted_traffic(args.workload, roof["kernel"])
     out = {
         "metric": "SDP solves/s at 1e-5 rel gap",
         "value": round(args.steps / dt, 6),

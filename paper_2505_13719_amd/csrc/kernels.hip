@@ -461,6 +461,62 @@ struct SpmmArgs {
   int32_t outrole;
 };
 
+// Stage a tile's entries of S u S^T into LDS: columns and pair values of the
+// upper CSR (coalesced), then the lower transpose, whose values are gathered
+// through the pair ids; SU entries per thread are loaded before any is
+// stored, so the gathers of a thread are in flight together.
+template <typename T>
+__device__ __forceinline__ void stage_entries(const InstDev &I, const T *__restrict__ m, int ku0, int nu, int kl0,
+                                              int nl, int32_t *s_col, T *s_m) {
+  constexpr int SU = 8;
+  for (int e0 = threadIdx.x; e0 < nu; e0 += BLOCK * SU) {
+    int c[SU];
+    T v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + u * BLOCK;
+      if (e < nu) {
+        c[u] = I.col_u[ku0 + e];
+        v[u] = m[ku0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + u * BLOCK;
+      if (e < nu) {
+        s_col[e] = c[u];
+        s_m[e] = v[u];
+      }
+    }
+  }
+  for (int e0 = threadIdx.x; e0 < nl; e0 += BLOCK * SU) {
+    int c[SU], id[SU];
+    T v[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + u * BLOCK;
+      if (e < nl) {
+        c[u] = I.col_l[kl0 + e];
+        id[u] = I.pid_l[kl0 + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + u * BLOCK;
+      if (e < nl) v[u] = m[id[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = e0 + u * BLOCK;
+      if (e < nl) {
+        s_col[nu + e] = c[u];
+        s_m[nu + e] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // operands of the row epilogue, loaded before the row's products so that
 // their latency overlaps the gathers
 template <typename T>
@@ -558,15 +614,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   if (nu + nl <= TILE_MAX_ENTRIES) {
     // stage the tile's columns and pair values of S u S^T (upper part, then
     // the lower transpose through its pair ids) with coalesced loads
-    for (int e = threadIdx.x; e < nu; e += BLOCK) {
-      s_col[e] = I.col_u[ku0 + e];
-      s_m[e] = m[ku0 + e];
-    }
-    for (int e = threadIdx.x; e < nl; e += BLOCK) {
-      s_col[nu + e] = I.col_l[kl0 + e];
-      s_m[nu + e] = m[I.pid_l[kl0 + e]];
-    }
-    __syncthreads();
+    stage_entries<T>(I, m, ku0, nu, kl0, nl, s_col, s_m);
     // a team of G * S lanes per row: S pair streams (power of two) when the
     // tile has fewer rows than the block has G-lane groups (long rows)
     int S = 1;
@@ -998,17 +1046,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tile
   const int ku0 = s_ru[0], nu = s_ru[nrows] - ku0;
   const int kl0 = s_rl[0], nl = s_rl[nrows] - kl0;
   const bool staged = nu + nl <= TILE_MAX_ENTRIES;
-  if (staged) {
-    for (int e = threadIdx.x; e < nu; e += BLOCK) {
-      s_col[e] = I.col_u[ku0 + e];
-      s_m[e] = I.m64[ku0 + e];
-    }
-    for (int e = threadIdx.x; e < nl; e += BLOCK) {
-      s_col[nu + e] = I.col_l[kl0 + e];
-      s_m[nu + e] = I.m64[I.pid_l[kl0 + e]];
-    }
-    __syncthreads();
-  }
+  if (staged) stage_entries<double>(I, I.m64, ku0, nu, kl0, nl, s_col, s_m);
   const int plog = staged ? max(0, (int)tl.plog_s - 2) : (int)tl.plog_s;
   const int TS = 1 << plog;
   const int team = threadIdx.x >> plog;

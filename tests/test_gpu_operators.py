@@ -35,7 +35,7 @@ CASES = list(_cases())
 
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
 @pytest.mark.parametrize("name,prob", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("r", [1, 5, 32])
+@pytest.mark.parametrize("r", [1, 3, 5, 32])
 def test_eval_and_adjoint_parity(prec, name, prob, r):
     d = dev()
     dt = torch.float64 if prec == H.FP64 else torch.float32
