@@ -213,7 +213,7 @@ def bench_served(args):
     reqs = [si.served_request(k, int(n), seed=5) for k, n in enumerate(sizes)]
     U0s = [si.gaussian_u0(int(n), 1000 + k) for k, n in enumerate(sizes)]
     t_gen = time.perf_counter() - t_gen
-    opts = H.options(eps=1e-5, rank_cap=32, profile=1)
+    opts = H.options(eps=1e-5, profile=1, verbose=args.verbose)
     rate = args.rate
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq)) if rate > 0 else np.zeros(nreq)
     pool = H.hallar_pool_create(int(args.budget_gb * (1 << 30)), args.max_active, H.FP32_MIXED, opts)
@@ -221,9 +221,15 @@ def bench_served(args):
     nxt = 0
     max_active = 0
     torch.cuda.synchronize()
+    print(f"[bench] served: {nreq} requests generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    t_print = 0.0
     while len(done) < nreq:
         now = time.perf_counter() - t0
+        if now - t_print > 5.0:
+            t_print = now
+            print(f"[bench] served t={now:.1f}s admitted={nxt} done={len(done)} active={max_active}",
+                  file=sys.stderr, flush=True)
         while nxt < nreq and arrivals[nxt] <= now:
             st = H.hallar_pool_admit(pool, reqs[nxt], nxt, U0=U0s[nxt])
             if st != "ok":
@@ -245,6 +251,26 @@ def bench_served(args):
     first = float(arrivals.min())
     last = max(v[0] for v in done.values())
     roof, table = roofline_from_profile(prof)
+    if roof:
+        roof["traffic"] = counted_traffic("served", roof["kernel"])
+    fifo = None
+    if args.fifo_sample > 0:
+        # the plain per-instance FP64 solver on the first requests of the same
+        # stream, one at a time on the same stream
+        k = min(args.fifo_sample, nreq)
+        ok64 = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for q in range(k):
+            h = H.hallar_create(reqs[q], H.FP64, H.options(eps=1e-5))
+            r = H.hallar_solve(h, torch.tensor(U0s[q], device="cuda:0"))
+            H.hallar_destroy(h)
+            ok64 += r["status"] == "ok"
+            print(f"[bench] fifo fp64 {q + 1}/{k}: n={reqs[q].n} {r['status']} {r['seconds']:.2f}s",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_fifo = time.perf_counter() - t1
+        fifo = {"requests": k, "solves_per_s": round(k / t_fifo, 4), "converged": ok64}
     out = {
         "metric": "SDP solves/s at 1e-5 rel gap",
         "value": round(nreq / (last - first), 4),
@@ -258,6 +284,7 @@ def bench_served(args):
                    "max_active": args.max_active},
         "served": {"p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
                    "converged": ok, "max_active": max_active, "gen_s": round(t_gen, 1)},
+        "fifo_fp64": fifo,
         "roofline": roof,
         "kernels": table,
     }
@@ -323,6 +350,8 @@ def main():
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--max-active", type=int, default=1024)
+    ap.add_argument("--fifo-sample", type=int, default=32,
+                    help="served: also solve this many requests one at a time with the plain FP64 solver")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",

@@ -19,6 +19,61 @@
 
 namespace hl {
 
+ResumeWorkers::~ResumeWorkers() {
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto &t : th_) t.join();
+}
+
+void ResumeWorkers::work(Job &j) {
+  for (int i; (i = j.next.fetch_add(1)) < j.n;) {
+    (*j.fn)(i);
+    j.done.fetch_add(1);
+  }
+}
+
+void ResumeWorkers::loop() {
+  uint64_t seen = 0;
+  for (;;) {
+    std::shared_ptr<Job> j;
+    {
+      std::unique_lock<std::mutex> lk(m_);
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      j = job_;
+    }
+    if (j) work(*j);
+  }
+}
+
+void ResumeWorkers::run(int n, const std::function<void(int)> &fn) {
+  if (th_.empty()) {
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int nt = (int)std::max(1u, std::min(8u, hc > 1 ? hc - 1 : 1u));
+    for (int t = 0; t < nt; ++t) th_.emplace_back([this] { loop(); });
+  }
+  auto j = std::make_shared<Job>();
+  j->fn = &fn;
+  j->n = n;
+  {
+    std::lock_guard<std::mutex> lk(m_);
+    job_ = j;
+    ++gen_;
+  }
+  cv_.notify_all();
+  work(*j);
+  while (j->done.load() < n) std::this_thread::yield();
+  // fn outlives no worker call: every index ran to completion, and a late
+  // worker finds j->next >= n and leaves without calling fn
+  std::lock_guard<std::mutex> lk(m_);
+  if (job_ == j) job_.reset();
+}
+
+
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -198,6 +253,11 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
   HL_TRY(hipHostMalloc((void **)&P.h_up, sizeof(double) * P.up_cap, hipHostMallocDefault), "hipHostMalloc upload");
   HL_TRY(hipMalloc((void **)&P.d_dl, sizeof(double) * P.dl_cap), "hipMalloc download");
   HL_TRY(hipHostMalloc((void **)&P.h_dl, sizeof(double) * P.dl_cap, hipHostMallocDefault), "hipHostMalloc download");
+  for (int q = 0; q < Pool::NSIDE; ++q) {
+    HL_TRY(hipStreamCreateWithFlags(&P.side[q], hipStreamNonBlocking), "hipStreamCreate");
+    HL_TRY(hipEventCreateWithFlags(&P.ev_join[q], hipEventDisableTiming), "hipEventCreate");
+  }
+  HL_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming), "hipEventCreate");
   P.profile = opts.profile != 0;
   if (P.profile) {
     P.events.resize(8192);
@@ -212,6 +272,10 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
 }
 
 void pool_release(Pool &P) {
+  if (P.opts.verbose && P.rounds > 0)
+    fprintf(stderr, "[hallar] pool: %lld rounds, host seconds prep %.3f launch %.3f wait %.3f resume %.3f\n",
+            (long long)P.rounds, P.t_prep, P.t_launch, P.t_wait, P.t_resume);
+  P.workers.reset();
   for (int s = 0; s < (int)P.slots.size(); ++s)
     if (P.slots[s]) slot_unload(P, s);
   auto fr = [](void *p) {
@@ -224,6 +288,14 @@ void pool_release(Pool &P) {
   frh(P.h_prm); frh(P.h_res); frh(P.h_tiles); frh(P.h_ilist); frh(P.h_up); frh(P.h_dl);
   for (auto &ev : P.events) (void)hipEventDestroy(ev);
   P.events.clear();
+  for (int q = 0; q < Pool::NSIDE; ++q) {
+    if (P.side[q]) (void)hipStreamDestroy(P.side[q]);
+    if (P.ev_join[q]) (void)hipEventDestroy(P.ev_join[q]);
+    P.side[q] = nullptr;
+    P.ev_join[q] = nullptr;
+  }
+  if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
+  P.ev_fork = nullptr;
   P.d_insts = nullptr;
   P.arena.release();
 }
@@ -421,16 +493,17 @@ struct ProfScope {
   Pool &P;
   int cls, e0 = -1;
   double bytes;
-  ProfScope(Pool &p, int c, double b) : P(p), cls(c), bytes(b) {
+  hipStream_t st;
+  ProfScope(Pool &p, int c, double b, hipStream_t s) : P(p), cls(c), bytes(b), st(s) {
     if (P.profile && P.ev_used + 2 <= (int)P.events.size()) {
       e0 = P.ev_used;
       P.ev_used += 2;
-      (void)hipEventRecord(P.events[e0], P.stream);
+      (void)hipEventRecord(P.events[e0], st);
     }
   }
   ~ProfScope() {
     if (e0 >= 0) {
-      (void)hipEventRecord(P.events[e0 + 1], P.stream);
+      (void)hipEventRecord(P.events[e0 + 1], st);
       P.recs.push_back(ProfRec{cls, e0, e0 + 1, bytes});
     }
   }
@@ -454,7 +527,7 @@ struct GroupBytes {
   double sddmm = 0, spmm_core = 0, urow = 0, lz_spmv = 0, vec_n8 = 0;
 };
 
-static void launch_group(Pool &P, const Group &g);
+static void launch_group(Pool &P, const Group &g, hipStream_t st);
 
 static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int R) {
   GroupBytes b;
@@ -471,8 +544,7 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
   return b;
 }
 
-static void launch_group(Pool &P, const Group &g) {
-  hipStream_t st = P.stream;
+static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   const Tile *T = P.d_tiles + g.t0;
   const int nt = (int)g.nt;
   const int32_t *IL = P.d_ilist + g.i0;
@@ -495,12 +567,12 @@ static void launch_group(Pool &P, const Group &g) {
     any_lr = any_lr || P.slots[s]->hp.r0 > 0;
   }
   auto red = [&](int op, int zsel) {
-    ProfScope ps(P, KC_REDUCE, 0.0);
+    ProfScope ps(P, KC_REDUCE, 0.0, st);
     op_reduce(st, IL, ni, D, op, zsel, R, 0);
   };
   auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
     {
-      ProfScope ps(P, KC_SDDMM, B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0));
+      ProfScope ps(P, KC_SDDMM, B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0), st);
       if (any_lr) op_lr_dots(prec, R, st, T, nt, D, xrole);
       op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
       if (gni > 0) {
@@ -513,18 +585,18 @@ static void launch_group(Pool &P, const Group &g) {
   switch (g.code) {
     case OP_TRIAL:
       {
-        ProfScope ps(P, KC_VEC, 4 * B.urow);
+        ProfScope ps(P, KC_VEC, 4 * B.urow, st);
         op_combo(prec, R, st, T, nt, D);
       }
       red(RDH_COMBO, 0);
       sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
       {
-        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow);
+        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
         op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
       }
       red(RDH_TRIAL_PROJ, 0);
       {
-        ProfScope ps(P, KC_VEC, 5 * B.urow);
+        ProfScope ps(P, KC_VEC, 5 * B.urow, st);
         op_proj(prec, R, st, T, nt, D);
       }
       red(RDH_PROJ_DOTS, 0);
@@ -532,7 +604,7 @@ static void launch_group(Pool &P, const Group &g) {
       break;
     case OP_GRAD:
       {
-        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow);
+        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
         op_spmm(prec, R, st, T, nt, D, RZ, 1, 1, 0, SPM_AIPP);
       }
       red(RDH_AIPP, 0);
@@ -542,28 +614,28 @@ static void launch_group(Pool &P, const Group &g) {
       break;
     case OP_COPY:
       {
-        ProfScope ps(P, KC_VEC, 2 * B.urow);
+        ProfScope ps(P, KC_VEC, 2 * B.urow, st);
         op_copy_scale(prec, R, st, T, nt, D, o.src, o.dst);
       }
       red(RDH_NORM, 0);
       break;
     case OP_PACK:
       {
-        ProfScope ps(P, KC_OTHER, 0.0);
+        ProfScope ps(P, KC_OTHER, 0.0, st);
         op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
       }
       red(RDH_NORM, 0);
       break;
     case OP_LZ_BEGIN:
       {
-        ProfScope ps(P, KC_OTHER, 0.0);
+        ProfScope ps(P, KC_OTHER, 0.0, st);
         if (dni > 0) op_pairvals(prec, st, DL, dni, g.maxp, D, 2, nullptr, 0);
         if (gni > 0) op_pairvals(prec, st, GL, gni, g.maxp, D, 2, nullptr, 1);
         op_lz_start(st, T, nt, D);
       }
       red(RDH_LZ_START, 0);
       {
-        ProfScope ps(P, KC_LZ_ORTH, 2 * B.vec_n8);
+        ProfScope ps(P, KC_LZ_ORTH, 2 * B.vec_n8, st);
         op_lz_first(st, T, nt, D);
       }
       break;
@@ -579,11 +651,11 @@ static void launch_group(Pool &P, const Group &g) {
             if (k < S.prm.lz_steps) vb += 2.0 * (S.prm.lz_j + k + 1) * S.hp.n * 8 + 3.0 * S.hp.n * 8;
           }
         {
-          ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv);
+          ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv, st);
           op_lz_spmv(st, T, nt, D, 0);
         }
         {
-          ProfScope ps(P, KC_LZ_ORTH, vb);
+          ProfScope ps(P, KC_LZ_ORTH, vb, st);
           // classical Gram-Schmidt against the whole basis; the second pass
           // runs only where the first removed most of w (the device decides
           // per instance, the skipped kernels return at once)
@@ -602,13 +674,13 @@ static void launch_group(Pool &P, const Group &g) {
     case OP_LZ_RITZ:
     case OP_LZ_RESTART:
       {
-        ProfScope ps(P, KC_LZ_ORTH, 0.0);
+        ProfScope ps(P, KC_LZ_ORTH, 0.0, st);
         op_lz_combine(st, T, nt, D, g.code == OP_LZ_RITZ ? 1 : 0);
       }
       break;
     case OP_FW_PREP:
       {
-        ProfScope ps(P, KC_OTHER, 0.0);
+        ProfScope ps(P, KC_OTHER, 0.0, st);
         op_fw_den(st, T, nt, D);
         if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
       }
@@ -616,27 +688,27 @@ static void launch_group(Pool &P, const Group &g) {
       break;
     case OP_FW_APPLY:
       {
-        ProfScope ps(P, KC_VEC, 0.0);
+        ProfScope ps(P, KC_VEC, 0.0, st);
         op_fw_apply(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
       }
       break;
     case OP_SETP:
       {
-        ProfScope ps(P, KC_VEC, 0.0);
+        ProfScope ps(P, KC_VEC, 0.0, st);
         op_set_p(st, IL, ni, g.maxm, D);
       }
       red(RDH_SETP, 0);
       break;
     case OP_GRAM:
       {
-        ProfScope ps(P, KC_OTHER, 0.0);
+        ProfScope ps(P, KC_OTHER, 0.0, st);
         op_gram(prec, R, st, T, nt, D, o.src);
       }
       red(RDH_GRAM, 0);
       break;
     case OP_ROTATE:
       {
-        ProfScope ps(P, KC_VEC, 0.0);
+        ProfScope ps(P, KC_VEC, 0.0, st);
         op_rotate(prec, g.R2, R, st, T, nt, D, o.src, o.dst);
       }
       break;
@@ -647,6 +719,7 @@ static void launch_group(Pool &P, const Group &g) {
 
 static hallar_status run_round(Pool &P, bool &did_work) {
   did_work = false;
+  const double tr0 = now_s();
   std::vector<int> ready;
   for (int s = 0; s < (int)P.slots.size(); ++s) {
     auto &sp = P.slots[s];
@@ -738,6 +811,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   }
   hipStream_t st = P.stream;
   std::string &err = P.err;
+  const double tr1 = now_s();
   if (P.insts_dirty) {
     HL_TRY(hipMemcpyAsync(P.d_insts, P.h_insts.data(), sizeof(InstDev) * P.max_slots, hipMemcpyHostToDevice, st),
            "upload descriptors");
@@ -747,23 +821,52 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   HL_TRY(hipMemcpyAsync(P.d_tiles, P.h_tiles, sizeof(Tile) * tpos, hipMemcpyHostToDevice, st), "upload tiles");
   HL_TRY(hipMemcpyAsync(P.d_ilist, P.h_ilist, sizeof(int32_t) * ipos, hipMemcpyHostToDevice, st), "upload ilist");
   if (up_used) HL_TRY(hipMemcpyAsync(P.d_up, P.h_up, sizeof(double) * up_used, hipMemcpyHostToDevice, st), "upload coef");
-  for (const Group &g : groups) launch_group(P, g);
+  if (groups.size() == 1) {
+    launch_group(P, groups[0], st);
+  } else {
+    // groups touch disjoint instances: spread them over the main and side
+    // streams, all after the uploads above, all joined before the downloads
+    HL_TRY(hipEventRecord(P.ev_fork, st), "fork");
+    const int ns = std::min<int>((int)groups.size(), 1 + Pool::NSIDE);
+    for (int q = 1; q < ns; ++q) HL_TRY(hipStreamWaitEvent(P.side[q - 1], P.ev_fork, 0), "fork wait");
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const int q = (int)(gi % ns);
+      launch_group(P, groups[gi], q == 0 ? st : P.side[q - 1]);
+    }
+    for (int q = 1; q < ns; ++q) {
+      HL_TRY(hipEventRecord(P.ev_join[q - 1], P.side[q - 1]), "join");
+      HL_TRY(hipStreamWaitEvent(st, P.ev_join[q - 1], 0), "join wait");
+    }
+  }
   HL_TRY(hipGetLastError(), "kernel launch");
   HL_TRY(hipMemcpyAsync(P.h_res, P.d_res, sizeof(InstRes) * maxs, hipMemcpyDeviceToHost, st), "download results");
   if (dl_used) HL_TRY(hipMemcpyAsync(P.h_dl, P.d_dl, sizeof(double) * dl_used, hipMemcpyDeviceToHost, st), "download");
+  const double tr2 = now_s();
   HL_TRY(hipStreamSynchronize(st), "round");
   if (P.profile) prof_collect(P);
+  const double tr3 = now_s();
   P.rounds++;
   did_work = true;
-  for (int s : run) {
-    Slot &S = *P.slots[s];
+  auto resume_one = [&](int i) {
+    Slot &S = *P.slots[run[i]];
     S.has_op = false;
     S.result.n_rounds++;
     if (S.op.dl_count) S.dl.assign(P.h_dl + S.op.dl_off, P.h_dl + S.op.dl_off + S.op.dl_count);
     auto h = S.resume;
     S.resume = {};
     h.resume();
+  };
+  if (run.size() >= 16) {
+    if (!P.workers) P.workers = std::make_unique<ResumeWorkers>();
+    P.workers->run((int)run.size(), resume_one);
+  } else {
+    for (int i = 0; i < (int)run.size(); ++i) resume_one(i);
   }
+  const double tr4 = now_s();
+  P.t_prep += tr1 - tr0;
+  P.t_launch += tr2 - tr1;
+  P.t_wait += tr3 - tr2;
+  P.t_resume += tr4 - tr3;
   return HALLAR_OK;
 }
 

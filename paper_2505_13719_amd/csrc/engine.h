@@ -1,8 +1,13 @@
 // Batched round executor and the pool of resident instances.
 #pragma once
+#include <atomic>
+#include <condition_variable>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
+#include <functional>
 
 #include "host.h"
 
@@ -24,6 +29,31 @@ class Arena {
   char *base_ = nullptr;
   size_t cap_ = 0, used_ = 0;
   std::map<size_t, size_t> free_;  // offset -> size
+};
+
+// Host worker threads that resume the solver coroutines of a round in
+// parallel (each coroutine touches only its own slot; the pool's shared
+// state is read-only while they run).
+class ResumeWorkers {
+ public:
+  ~ResumeWorkers();
+  // run fn(i) for i in [0, n) on the workers and the calling thread
+  void run(int n, const std::function<void(int)> &fn);
+
+ private:
+  struct Job {
+    const std::function<void(int)> *fn;
+    int n;
+    std::atomic<int> next{0}, done{0};
+  };
+  void loop();
+  static void work(Job &j);
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+  std::shared_ptr<Job> job_;  // a worker holds its own reference while it works on a job
 };
 
 // kernel classes of the profile
@@ -68,6 +98,14 @@ struct Pool {
   std::vector<ProfRec> recs;
   double prof_ms[KC_N] = {0}, prof_bytes[KC_N] = {0};
   int64_t prof_n[KC_N] = {0};
+  // side streams (default priority) on which the groups of a round run
+  // concurrently, joined to `stream` by events
+  static constexpr int NSIDE = 3;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[NSIDE] = {};
+  std::unique_ptr<ResumeWorkers> workers;
+  // host-side seconds per round phase (reported at release when opts.verbose)
+  double t_prep = 0, t_launch = 0, t_wait = 0, t_resume = 0;
 };
 
 // lifetime

@@ -74,13 +74,20 @@ __device__ __forceinline__ T *role_ptr(const InstDev &I, const InstParams &P, in
 
 
 // Tile of this workgroup.  The hardware deals workgroups to the 8 XCDs in
-// turn (workgroup b to XCD b mod 8); this bijection gives each XCD a
-// contiguous run of tiles, so neighbouring rows gathered by the sparse
-// kernels stay in that XCD's L2.
+// turn (workgroup b to XCD b mod 8).  Tiles are grouped in chunks of 16
+// consecutive tiles and XCD x takes chunks x, x + 8, x + 16, ...: neighbouring
+// rows gathered by the sparse kernels stay in one XCD's L2 within a chunk,
+// while every XCD gets chunks from the whole row range, so work stays
+// balanced when it is concentrated in part of the rows (a bipartite pattern
+// keeps all upper pairs in its first block).  Bijective: full groups of
+// 8 x 16 tiles are permuted, the remainder maps to itself.
 __device__ __forceinline__ int tile_index() {
+  constexpr int C = 16;
   const int nb = gridDim.x, b = blockIdx.x;
-  const int x = b & 7, k = b >> 3, q = nb >> 3, rem = nb & 7;
-  return x * q + min(x, rem) + k;
+  const int main = nb - nb % (8 * C);
+  if (b >= main) return b;
+  const int x = b & 7, k = b >> 3;
+  return (x + 8 * (k / C)) * C + k % C;
 }
 
 // ---------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 // eqs. def: support S ell and index list), the symmetric pattern S u S^T of
 // the adjoint (Algorithm 4), and the tile schedule.
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -254,7 +255,7 @@ static int plog_for(double avg) {
 
 void build_tiles(HostProblem &hp) {
   constexpr int64_t kMaxTiles = 2048;
-  constexpr int32_t kMinRows = 16;
+  constexpr int32_t kMinRows = 64;
   const int32_t n = hp.n;
   const int32_t row_target =
       std::min<int32_t>(TILE_MAX_ROWS, std::max<int32_t>(kMinRows, (int32_t)((n + kMaxTiles - 1) / kMaxTiles)));
@@ -284,51 +285,112 @@ void build_tiles(HostProblem &hp) {
   }
 }
 
-// cyclic Jacobi eigen solver for small symmetric matrices
+// Symmetric eigen decomposition of a small dense matrix (the Rayleigh-Ritz
+// matrices of the Lanczos solver and the Gram matrices of U): Householder
+// reduction to tridiagonal form with the transformations accumulated, then
+// implicit QL iterations with Wilkinson shifts on the tridiagonal matrix,
+// rotating the accumulated basis; eigenpairs sorted ascending.
 void sym_eig(int n, const double *A, double *w, double *Q) {
+  if (n <= 0) return;
   std::vector<double> a(A, A + (size_t)n * n);
-  std::vector<double> v((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
-        tot += x;
-        if (i != j) off += x;
+  std::vector<double> z((size_t)n * n, 0.0);  // accumulated orthogonal basis, row-major
+  for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
+  auto at = [&](int i, int j) -> double & { return a[(size_t)i * n + j]; };
+  auto zt = [&](int i, int j) -> double & { return z[(size_t)i * n + j]; };
+  std::vector<double> v(n), pv(n);
+  // Householder: zero column k below the subdiagonal, k = 0 .. n-3
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha += at(i, k) * at(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    const double x0 = at(k + 1, k);
+    const double beta = x0 >= 0.0 ? -alpha : alpha;  // new subdiagonal entry
+    // v = x - beta e1 (on indices k+1..n-1), tau = 2 / (v^T v)
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      v[i] = at(i, k) - (i == k + 1 ? beta : 0.0);
+      vv += v[i] * v[i];
+    }
+    if (vv == 0.0) continue;
+    const double tau = 2.0 / vv;
+    // p = tau A v (trailing block), K = tau/2 v^T p, q = p - K v
+    for (int i = k + 1; i < n; ++i) {
+      double sacc = 0.0;
+      for (int j = k + 1; j < n; ++j) sacc += at(i, j) * v[j];
+      pv[i] = tau * sacc;
+    }
+    double vp = 0.0;
+    for (int i = k + 1; i < n; ++i) vp += v[i] * pv[i];
+    const double K = 0.5 * tau * vp;
+    for (int i = k + 1; i < n; ++i) pv[i] -= K * v[i];
+    // A <- A - v q^T - q v^T on the trailing block; column / row k
+    for (int i = k + 1; i < n; ++i)
+      for (int j = k + 1; j < n; ++j) at(i, j) -= v[i] * pv[j] + pv[i] * v[j];
+    at(k + 1, k) = at(k, k + 1) = beta;
+    for (int i = k + 2; i < n; ++i) at(i, k) = at(k, i) = 0.0;
+    // Z <- Z (I - tau v v^T)
+    for (int r = 0; r < n; ++r) {
+      double sacc = 0.0;
+      for (int j = k + 1; j < n; ++j) sacc += zt(r, j) * v[j];
+      sacc *= tau;
+      for (int j = k + 1; j < n; ++j) zt(r, j) -= sacc * v[j];
+    }
+  }
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = at(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = at(i + 1, i);
+  // implicit QL with Wilkinson shifts; e[i] couples d[i] and d[i+1]
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
       }
-    if (off <= 1e-30 * tot || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = a[(size_t)p * n + q];
-        if (apq == 0.0) continue;
-        const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
-          a[(size_t)k * n + p] = c * akp - s * akq;
-          a[(size_t)k * n + q] = s * akp + c * akq;
+      if (m == l) break;
+      // shift from the trailing 2x2 block of the unreduced part starting at l
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // deflation inside the sweep
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          break;
         }
-        for (int k = 0; k < n; ++k) {
-          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
-          a[(size_t)p * n + k] = c * apk - s * aqk;
-          a[(size_t)q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
-          v[(size_t)k * n + p] = c * vkp - s * vkq;
-          v[(size_t)k * n + q] = s * vkp + c * vkq;
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {  // rotate basis columns i, i+1
+          f = zt(k, i + 1);
+          zt(k, i + 1) = s * zt(k, i) + c * f;
+          zt(k, i) = c * zt(k, i) - s * f;
         }
       }
+      if (r == 0.0 && i >= l) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
   }
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
-  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a[(size_t)x * n + x] < a[(size_t)y * n + y]; });
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int c = 0; c < n; ++c) {
-    w[c] = a[(size_t)idx[c] * n + idx[c]];
-    for (int k = 0; k < n; ++k) Q[(size_t)k * n + c] = v[(size_t)k * n + idx[c]];
+    w[c] = d[idx[c]];
+    for (int k = 0; k < n; ++k) Q[(size_t)k * n + c] = z[(size_t)k * n + idx[c]];
   }
 }
 

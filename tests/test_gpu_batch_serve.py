@@ -97,3 +97,30 @@ def test_pool_admission_and_mix():
         a = _alone(p, prec)
         for key in KEYS:
             assert a[key] == done[k][key], (k, key, a[key], done[k][key])
+
+
+def test_large_batch_equals_alone():
+    """A batch wide enough that the host resumes its solver coroutines on
+    worker threads: results stay bit-identical to solving alone."""
+    d = dev()
+    rng = np.random.default_rng(9)
+    probs = []
+    for k in range(20):
+        n = int(rng.integers(30, 400))
+        i, j = si.er_edges(n, 6.0 / (n - 1), rng)
+        probs.append(si.maxcut_problem(n, i, j, si.pm1_weights(i.size, rng)))
+    probs.append(si.theta_problem(16, *si.hypercube_edges(4)))
+    probs.append(si.mc_planted(40, 50, 2, 900, seed=2))
+    prec = H.FP32_MIXED
+    alone = [_alone(p, prec) for p in probs]
+    hs = [H.hallar_create(p, prec, H.options(eps=1e-5)) for p in probs]
+    try:
+        U0s = [torch.tensor(si.gaussian_u0(p.n, 3), device=d) for p in probs]
+        batch = H.hallar_solve_batch(hs, U0s)
+    finally:
+        for h in hs:
+            H.hallar_destroy(h)
+    for a, b in zip(alone, batch):
+        for k in KEYS:
+            assert a[k] == b[k], (k, a[k], b[k])
+    assert sum(a["status"] == "ok" for a in alone) >= len(probs) - 1
