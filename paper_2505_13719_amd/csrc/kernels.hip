@@ -597,7 +597,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
   constexpr int NQ = MODE == SP_AIPP ? 4 : (MODE == SP_TRIAL ? 2 : 1);
-  constexpr int UN = 8;  // gathers in flight per lane
+  constexpr int UN = 4;  // gathers in flight per lane (measured: 4 beats 8 on the torus and MC)
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   __shared__ int32_t s_col[TILE_MAX_ENTRIES];
   __shared__ T s_m[TILE_MAX_ENTRIES];
