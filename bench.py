@@ -150,10 +150,11 @@ def bench_solve(args):
     if args.precision:
         prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
     dev = torch.device("cuda:0")
-    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, verbose=args.verbose, **kw)
+    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, verbose=args.verbose, autotune=args.autotune, **kw)
     t_build = time.perf_counter()
     h = H.hallar_create(prob, prec, opts)
     t_build = time.perf_counter() - t_build
+    schedule = dict(zip(("min_rows", "ent_cap", "ntiles"), H.hallar_schedule(h)))
     U0 = torch.tensor(si.gaussian_u0(prob.n, 7), device=dev)
     res = None
     for _ in range(args.warmup):
@@ -193,6 +194,7 @@ def bench_solve(args):
         "roofline": roof,
         "kernels": table,
         "create_s": round(t_build, 2),
+        "schedule": dict(schedule, autotuned=bool(args.autotune)),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, res, budget_s=args.cpu_budget)
@@ -345,6 +347,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0, help="solver progress on stderr (1: outer, 2: HLR)")
     ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
+    ap.add_argument("--autotune", type=int, default=0, help="1: tune the tile schedule at create (timed outside the steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--served-requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")

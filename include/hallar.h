@@ -101,6 +101,11 @@ typedef struct {
   uint64_t seed;                    /* Lanczos start vectors and default U0 */
   int32_t verbose;
   int32_t profile;                  /* 1: time every kernel class with HIP events (see hallar_profile) */
+  int32_t autotune;                 /* 1: hallar_create times candidate tile schedules on the instance and
+                                       keeps the fastest (see hallar_schedule); 0: the default schedule.
+                                       The schedule fixes the order of the partial sums, so results of
+                                       differently tuned handles agree to rounding, not bit for bit. */
+  int32_t pad_;
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);
@@ -134,6 +139,14 @@ typedef struct {
  * Errors: E_INVALID (bad shape/index), E_UNSUPPORTED, E_OOM, E_HIP. */
 hallar_status hallar_create(const hallar_problem *prob, hallar_precision prec,
                             const hallar_options *opts, void *stream, hallar_t *out);
+/* The tile schedule of a handle: rows of a tile are contiguous, at least
+ * *min_rows of them (more on large instances) and at most *ent_cap entries of
+ * S u S^T; *ntiles tiles in all.  Segment-indexed kernels walk these tiles
+ * (one workgroup per tile) and reduce their partial sums in tile order; with
+ * opts.autotune the schedule is the fastest of the candidates timed on the
+ * instance at create.  E_INVALID on a bad handle; NULL outputs are skipped. */
+hallar_status hallar_schedule(hallar_t h, int32_t *min_rows, int32_t *ent_cap, int64_t *ntiles);
+
 hallar_status hallar_destroy(hallar_t h);
 const char *hallar_last_error(hallar_t h);
 

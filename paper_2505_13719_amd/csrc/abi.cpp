@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/hallar.h.
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <mutex>
 #include <random>
 
@@ -94,6 +95,110 @@ void hallar_default_options(hallar_options *o) {
 
 const char *hallar_last_error(hallar_t h) { return h ? h->err.c_str() : g_err.c_str(); }
 
+namespace {
+
+// Autotuner of the tile schedule: every candidate (minimum rows, entry cap)
+// builds its tiles, loads the instance into a scratch pool and times the
+// SDDMM (hallar_eval_AUUt) and SpMM (hallar_adjoint_spmm) entry points at two
+// widths with HIP events; the fastest candidate wins (ties keep the earlier,
+// the default comes first).
+hallar_status tune_schedule(hl::HostProblem &hp, int prec, const hallar_options &o, hipStream_t st, std::string &msg) {
+  struct Cand {
+    int32_t min_rows, ent_cap;
+  };
+  static const Cand kCands[] = {{64, 2048}, {16, 2048}, {256, 2048}, {64, 1024}, {16, 512}, {256, 1024}};
+  const size_t sz = prec == 0 ? 8 : 4;
+  const int rcap = hl::rcap_for(o, prec);
+  const int widths[2] = {std::min(4, rcap), std::min(16, rcap)};
+  const size_t n = hp.n;
+  void *dU = nullptr, *dW = nullptr;
+  double *dT = nullptr, *dp = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    if (dU) (void)hipFree(dU);
+    if (dW) (void)hipFree(dW);
+    if (dT) (void)hipFree(dT);
+    if (dp) (void)hipFree(dp);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&dU, n * 16 * sz) != hipSuccess || hipMalloc(&dW, n * 16 * sz) != hipSuccess ||
+      hipMalloc((void **)&dT, (hp.m + 1) * 8) != hipSuccess || hipMalloc((void **)&dp, std::max(hp.m, 1) * 8) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    msg = "autotune: device allocation failed";
+    return HALLAR_E_OOM;
+  }
+  {
+    // deterministic operands: U entries in [-1, 1), p entries in [-1, 1)
+    std::vector<float> uf;
+    std::vector<double> ud, pv(std::max(hp.m, 1));
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    auto nxt = [&] {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    };
+    if (prec == 0) {
+      ud.resize(n * 16);
+      for (auto &v : ud) v = nxt();
+      (void)hipMemcpy(dU, ud.data(), ud.size() * 8, hipMemcpyHostToDevice);
+    } else {
+      uf.resize(n * 16);
+      for (auto &v : uf) v = (float)nxt();
+      (void)hipMemcpy(dU, uf.data(), uf.size() * 4, hipMemcpyHostToDevice);
+    }
+    for (auto &v : pv) v = nxt();
+    (void)hipMemcpy(dp, pv.data(), pv.size() * 8, hipMemcpyHostToDevice);
+  }
+  hallar_options to = o;
+  to.profile = 0;
+  to.verbose = 0;
+  int best = 0;
+  float best_ms = 0.f;
+  for (int c = 0; c < (int)(sizeof(kCands) / sizeof(kCands[0])); ++c) {
+    hl::HostProblem h2 = hp;
+    h2.tile_min_rows = kCands[c].min_rows;
+    h2.tile_ent_cap = kCands[c].ent_cap;
+    hl::build_tiles(h2);
+    hl::Pool P;
+    hallar_status s = hl::pool_init(P, 1, prec, to, st, 0, (int64_t)h2.tiles.size(), msg);
+    if (s == HALLAR_OK) s = hl::slot_load(P, 0, std::move(h2), msg);
+    float ms = -1.f;
+    if (s == HALLAR_OK) {
+      for (int rep = 0; rep < 4 && s == HALLAR_OK; ++rep) {
+        if (rep == 1) (void)hipEventRecord(e0, st);
+        for (int wi = 0; wi < 2 && s == HALLAR_OK; ++wi) {
+          s = hl::op_eval_AUUt(P, 0, dU, widths[wi], widths[wi], dT, st);
+          if (s == HALLAR_OK) s = hl::op_adjoint(P, 0, dp, dU, widths[wi], widths[wi], dW, widths[wi], st);
+        }
+      }
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      if (s == HALLAR_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    hl::pool_release(P);
+    if (s != HALLAR_OK) {
+      cleanup();
+      return s;
+    }
+    if (o.verbose)
+      fprintf(stderr, "[hallar] autotune: min_rows %d ent_cap %d: %.3f ms\n", kCands[c].min_rows, kCands[c].ent_cap, ms);
+    if (c == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  cleanup();
+  hp.tile_min_rows = kCands[best].min_rows;
+  hp.tile_ent_cap = kCands[best].ent_cap;
+  hl::build_tiles(hp);
+  return HALLAR_OK;
+}
+
+}  // namespace
+
 hallar_status hallar_create(const hallar_problem *prob, hallar_precision prec, const hallar_options *opts, void *stream,
                             hallar_t *out) {
   if (!out) return fail(nullptr, HALLAR_E_INVALID, "out is NULL");
@@ -108,6 +213,10 @@ hallar_status hallar_create(const hallar_problem *prob, hallar_precision prec, c
   hallar_status code;
   msg = hl::build_host_problem(prob, hp, &code);
   if (code != HALLAR_OK) return fail(nullptr, code, msg);
+  if (o.autotune) {
+    code = tune_schedule(hp, (int)prec, o, (hipStream_t)stream, msg);
+    if (code != HALLAR_OK) return fail(nullptr, code, msg);
+  }
   auto h = new (std::nothrow) hallar_s;
   if (!h) return fail(nullptr, HALLAR_E_OOM, "out of host memory");
   h->prec = (int)prec;
@@ -134,6 +243,15 @@ hallar_status hallar_destroy(hallar_t h) {
   (void)hipStreamSynchronize(h->P.stream);
   hl::pool_release(h->P);
   delete h;
+  return HALLAR_OK;
+}
+
+hallar_status hallar_schedule(hallar_t h, int32_t *min_rows, int32_t *ent_cap, int64_t *ntiles) {
+  if (!h || !h->P.slots[0]) return fail(h, HALLAR_E_INVALID, "bad handle");
+  const auto &hp = h->P.slots[0]->hp;
+  if (min_rows) *min_rows = hp.tile_min_rows;
+  if (ent_cap) *ent_cap = hp.tile_ent_cap;
+  if (ntiles) *ntiles = (int64_t)hp.tiles.size();
   return HALLAR_OK;
 }
 

@@ -31,8 +31,10 @@ struct HostProblem {
   std::vector<double> K0, D0;
   std::vector<double> b;
   double b_l1 = 0.0, c_l1 = 0.0;
-  // tiles (row ranges) and their pair-stream choices
+  // tiles (row ranges) and their pair-stream choices; the schedule's two
+  // parameters (defaults, or the autotuner's choice)
   std::vector<Tile> tiles;
+  int32_t tile_min_rows = 64, tile_ent_cap = TILE_MAX_ENTRIES;
 };
 
 // Returns "" on success or an error message; *code receives the status.

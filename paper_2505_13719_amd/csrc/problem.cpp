@@ -240,9 +240,10 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
 }
 
 // Tile schedule: contiguous row ranges of at most TILE_MAX_ROWS rows and
-// TILE_MAX_ENTRIES entries of S u S^T (a row longer than that is a tile of its
-// own), aiming at about kMaxTiles tiles per large instance (8 workgroups per
-// CU) and at least kMinRows rows per tile for small ones.  Per tile, the
+// tile_ent_cap (<= TILE_MAX_ENTRIES) entries of S u S^T (a row longer than
+// that is a tile of its own), aiming at about kMaxTiles tiles per large
+// instance (8 workgroups per CU) and at least tile_min_rows rows per tile for
+// small ones.  Per tile, the
 // number of pair streams per row (power of two near the mean row length) is
 // kept for the kernels that walk rows with teams.  The schedule depends on
 // the instance only, so a batched instance reduces in the same order as a
@@ -255,7 +256,8 @@ static int plog_for(double avg) {
 
 void build_tiles(HostProblem &hp) {
   constexpr int64_t kMaxTiles = 2048;
-  constexpr int32_t kMinRows = 64;
+  const int32_t kMinRows = std::max<int32_t>(1, std::min<int32_t>(hp.tile_min_rows, TILE_MAX_ROWS));
+  const int64_t kEntCap = std::max<int32_t>(1, std::min<int32_t>(hp.tile_ent_cap, TILE_MAX_ENTRIES));
   const int32_t n = hp.n;
   const int32_t row_target =
       std::min<int32_t>(TILE_MAX_ROWS, std::max<int32_t>(kMinRows, (int32_t)((n + kMaxTiles - 1) / kMaxTiles)));
@@ -266,7 +268,7 @@ void build_tiles(HostProblem &hp) {
     int32_t r1 = r0;
     while (r1 < n && (r1 - r0) < row_target) {
       const int64_t e = (hp.rowptr_u[r1 + 1] - hp.rowptr_u[r1]) + (hp.rowptr_l[r1 + 1] - hp.rowptr_l[r1]);
-      if (r1 > r0 && ent + e > TILE_MAX_ENTRIES) break;
+      if (r1 > r0 && ent + e > kEntCap) break;
       ent += e;
       ++r1;
     }

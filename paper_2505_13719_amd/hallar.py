@@ -41,7 +41,8 @@ class hallar_options(C.Structure):
                 ("hlr_max_iter", C.c_int32), ("outer_max_iter", C.c_int32), ("eig_tol", C.c_double),
                 ("eig_frac", C.c_double), ("eig_kmax", C.c_int32), ("eig_max_iter", C.c_int32),
                 ("rank_cap", C.c_int32), ("drop_tol", C.c_double), ("time_limit", C.c_double),
-                ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32)]
+                ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32), ("autotune", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class hallar_result(C.Structure):
@@ -66,7 +67,7 @@ EXPORTS = ["hallar_default_options", "hallar_create", "hallar_destroy", "hallar_
            "hallar_eval_AUUt", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
            "hallar_solve_batch", "hallar_footprint", "hallar_pool_create", "hallar_pool_destroy",
            "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage", "hallar_profile",
-           "hallar_pool_profile"]
+           "hallar_pool_profile", "hallar_schedule"]
 
 _lib = None
 
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.hallar_last_error.argtypes = [vp]
     L.hallar_last_error.restype = C.c_char_p
     L.hallar_describe.argtypes = [vp, i64p, i64p, i64p]
+    L.hallar_schedule.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p]
     L.hallar_eval_AUUt.argtypes = [vp, vp, C.c_int32, C.c_int64, vp, vp]
     L.hallar_adjoint_spmm.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, vp, C.c_int64, vp]
     L.hallar_min_eig.argtypes = [vp, vp, vp, C.c_double, C.c_int32, f64p, vp, C.POINTER(hallar_eig_info), vp]
@@ -369,6 +371,13 @@ def _profile(fn, obj, reset):
     ms, nl, by = (C.c_double * n)(), (C.c_int64 * n)(), (C.c_double * n)()
     _check(fn(obj, ms, nl, by, n, 1 if reset else 0))
     return {k: dict(ms=ms[i], launches=nl[i], bytes=by[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def hallar_schedule(h):
+    """(min_rows, ent_cap, ntiles) of the handle's tile schedule."""
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(load().hallar_schedule(h, C.byref(a), C.byref(b), C.byref(c)), h)
+    return a.value, b.value, c.value
 
 
 def hallar_profile(h, reset=False):

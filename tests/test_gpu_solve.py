@@ -152,3 +152,26 @@ def test_eps_1e5_within_a_posteriori_bound(prec):
     r = oracle.a_tilde(prob, U)[1:] - prob.b
     bound = res["gap"] * (1 + abs(res["pval"]) + abs(res["dval"])) + abs(p @ r) + 1e-6 * abs(res["pval"])
     assert abs(res["pval"] - REFS[name]["pval"]) <= bound
+
+
+def test_autotuned_schedule_solves_alike():
+    """opts.autotune = 1 picks one of the candidate tile schedules by timing
+    the SDDMM and SpMM entry points; the solve agrees with the default
+    schedule's to the solve tolerance (partial-sum order differs)."""
+    d = dev()
+    prob = si.mc_planted(300, 400, 2, 20000, seed=8)
+    res = {}
+    for tune in (0, 1):
+        h = H.hallar_create(prob, H.FP32_MIXED, H.options(eps=1e-5, autotune=tune))
+        try:
+            mr, cap, nt = H.hallar_schedule(h)
+            assert (mr, cap) in [(64, 2048), (16, 2048), (256, 2048), (64, 1024), (16, 512), (256, 1024)]
+            if not tune:
+                assert (mr, cap) == (64, 2048)
+            assert nt >= 1
+            res[tune] = H.hallar_solve(h, torch.tensor(si.gaussian_u0(prob.n, 7), device=d))
+        finally:
+            H.hallar_destroy(h)
+    for r in res.values():
+        assert r["status"] == "ok", r
+    assert abs(res[0]["pval"] - res[1]["pval"]) <= 1e-5 * (1 + abs(res[0]["pval"]))
