@@ -158,7 +158,7 @@ struct Carve {
 };
 
 struct Layout {
-  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, b, K0, K064, D0;
+  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, b, K0, K064, D0, c_diag;
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, gram, tiles, ilist;
   size_t total;
@@ -184,6 +184,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.col_l = c.take(nl * 4);
   L.pid_l = c.take(nl * 4);
   L.b = c.take(m * 8);
+  L.c_diag = c.take(hp.c_diag_only ? n * 8 : 0);
   L.K0 = c.take(n * hp.r0 * sz);
   L.K064 = c.take(n * hp.r0 * 8);
   L.D0 = c.take(hp.r0 * hp.r0 * 8);
@@ -359,6 +360,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   put(base, L.pa64, h.pa, st);
   put(base, L.rowptr_l, h.rowptr_l, st);
   put(base, L.col_l, h.col_l, st);
+  put(base, L.c_diag, h.c_diag, st);
   put(base, L.pid_l, h.pid_l, st);
   put(base, L.b, h.b, st);
   conv(h.K0, L.K0);
@@ -401,6 +403,10 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.pa = at(L.pa);
   D.c64 = h.has_c ? (const double *)at(L.c64) : nullptr;
   D.pa64 = (const double *)at(L.pa64);
+  D.pa_uniform = h.pa_uniform ? 1 : 0;
+  D.pa_const = h.pa_const;
+  D.c_diag_only = h.c_diag_only ? 1 : 0;
+  D.c_diag = h.c_diag_only ? (const double *)at(L.c_diag) : nullptr;
   D.b = (const double *)at(L.b);
   D.rowptr_l = (const int32_t *)at(L.rowptr_l);
   D.col_l = (const int32_t *)at(L.col_l);
@@ -536,7 +542,9 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
     const HostProblem &h = P.slots[s]->hp;
     const double n = h.n, Pp = (double)h.npairs, nl = (double)h.nlower, m = h.m;
     b.urow += n * R * sz;
-    b.sddmm += n * R * sz + (n + 1) * 4 + Pp * (4 + (h.direct ? 4 + sz : 0) + (h.has_c ? sz : 0)) + 16 * m;
+    b.sddmm += n * R * sz + (n + 1) * 4 + Pp * (4 + (h.direct ? 4 + (h.pa_uniform ? 0 : sz) : 0) +
+                                                 (h.has_c && !h.c_diag_only ? sz : 0)) +
+               (h.c_diag_only ? 8 * n : 0) + 16 * m;
     b.spmm_core += n * R * sz + 2 * (n + 1) * 4 + Pp * (4 + sz) + nl * 8;
     b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 8 + 2 * (n + 1) * 4;
     b.vec_n8 += n * 8;

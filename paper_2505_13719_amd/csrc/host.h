@@ -23,6 +23,10 @@ struct HostProblem {
   std::vector<double> c_u, pa;                 // C_ij and (A_l)_ij of the pair's constraint
   std::vector<int32_t> rowptr_l, col_l, pid_l;
   bool direct = true, has_c = false;
+  bool pa_uniform = false;      // every constrained pair has the coefficient pa_const (direct mode)
+  double pa_const = 0.0;
+  bool c_diag_only = false;     // C's sparse part is diagonal: c_diag[i] = C_ii
+  std::vector<double> c_diag;
   // general mode (a constraint with several pairs or a pair in several constraints)
   std::vector<int32_t> eptr, econ, cptr, cent, epair;
   std::vector<double> ea, ew;

@@ -97,6 +97,9 @@ struct InstDev {
   const int32_t *rowptr_u, *col_u, *pcon;   // upper CSR over S (pair k = position), constraint of pair (0 = none)
   const int32_t *rowptr_l, *col_l, *pid_l;  // strictly-lower transpose of S with pair ids
   const void *c_u, *pa;                     // operator type: C_ij per pair, (A_l)_ij of the pair's constraint
+  int32_t pa_uniform, c_diag_only;          // the SDDMM reads pa_const / c_diag instead of pa / c_u
+  double pa_const;
+  const double *c_diag;                     // length n when c_diag_only
   const double *c64, *pa64, *b;             // FP64 copies, b (length m)
   const void *K0; const double *D0;         // low-rank objective: K0 n x r0 (op type), D0 r0 x r0
   const double *K064;                       // FP64 K0 for the Lanczos SpMV

@@ -152,11 +152,12 @@ __device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, con
         }
         ii[u] = tl.row0 + lo;
         jj[u] = I.col_u[k];
-        cv[u] = cu ? (double)cu[k] : 0.0;
+        if (I.c_diag_only) cv[u] = ii[u] == jj[u] ? I.c_diag[ii[u]] : 0.0;
+        else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
           l[u] = I.pcon[k];
           if (l[u] > 0) {
-            av[u] = (double)pa[k];
+            av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
             bl[u] = I.b[l[u] - 1];
             pl[u] = I.p[l[u] - 1];
           }
@@ -259,12 +260,14 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
           else hi = mid - 1;
         }
         s_i[pb] = tl.row0 + lo;
-        s_j[pb] = I.col_u[k];
-        cv[u] = cu ? (double)cu[k] : 0.0;
+        const int jc = I.col_u[k];
+        s_j[pb] = jc;
+        if (I.c_diag_only) cv[u] = tl.row0 + lo == jc ? I.c_diag[jc] : 0.0;
+        else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
           l[u] = I.pcon[k];
           if (l[u] > 0) {
-            av[u] = (double)pa[k];
+            av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
             bl[u] = I.b[l[u] - 1];
             pl[u] = I.p[l[u] - 1];
           }

@@ -110,6 +110,39 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
   hp.direct = direct;
   hp.has_c = has_c;
   hp.nentries = nent;
+  // structure the SDDMM can exploit without reading per-pair arrays: one
+  // coefficient shared by every constrained pair (MaxCut 1, theta and matrix
+  // completion 1/2), and a sparse objective that lives on the diagonal only
+  // (matrix completion's I/2)
+  {
+    bool uni = direct, first = true;
+    double a0 = 0.0;
+    for (int64_t k = 0; k < P && uni; ++k)
+      if (hp.pcon[k] > 0) {
+        if (first) {
+          a0 = hp.pa[k];
+          first = false;
+        } else if (hp.pa[k] != a0) {
+          uni = false;
+        }
+      }
+    hp.pa_uniform = uni && !first;
+    hp.pa_const = a0;
+    bool diag = has_c;
+    for (int32_t i = 0; i < n && diag; ++i)
+      for (int32_t k = hp.rowptr_u[i]; k < hp.rowptr_u[i + 1]; ++k)
+        if (hp.col_u[k] != i && hp.c_u[k] != 0.0) {
+          diag = false;
+          break;
+        }
+    hp.c_diag_only = diag;
+    if (diag) {
+      hp.c_diag.assign(n, 0.0);
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = hp.rowptr_u[i]; k < hp.rowptr_u[i + 1]; ++k)
+          if (hp.col_u[k] == i) hp.c_diag[i] = hp.c_u[k];
+    }
+  }
   if (!direct) {
     hp.eptr.assign(P + 1, 0);
     hp.econ.resize(nent);
