@@ -650,29 +650,32 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     case OP_LZ_STEPS:
       // instances with fewer steps skip the extra ones (their lz_steps counter reaches 0)
       for (int k = 0; k < g.steps; ++k) {
-        // algorithmic bytes of one Gram-Schmidt pass (dots + update over the
-        // basis and w); a second pass, when the device runs it, is overhead
-        double vb = 0;
+        // algorithmic bytes of one Gram-Schmidt pass: a sweep of the basis for
+        // the dots (fused into the SpMV) and one for the update, plus w; a
+        // second pass, when the device runs it, is overhead
+        double vsweep = 0, wbytes = 0;
         if (P.profile)
           for (int s : g.slots) {
             const Slot &S = *P.slots[s];
-            if (k < S.prm.lz_steps) vb += 2.0 * (S.prm.lz_j + k + 1) * S.hp.n * 8 + 3.0 * S.hp.n * 8;
+            if (k < S.prm.lz_steps) {
+              vsweep += (double)(S.prm.lz_j + k + 1) * S.hp.n * 8;
+              wbytes += 3.0 * S.hp.n * 8;
+            }
           }
+        const double vb = vsweep + wbytes;
         {
-          ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv, st);
-          op_lz_spmv(st, T, nt, D, 0);
+          // SpMV fused with the first Gram-Schmidt dots
+          ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv + vsweep, st);
+          op_lz_spmv_dots(st, T, nt, D);
         }
         {
-          ProfScope ps(P, KC_LZ_ORTH, vb, st);
           // classical Gram-Schmidt against the whole basis; the second pass
           // runs only where the first removed most of w (the device decides
           // per instance, the skipped kernels return at once)
-          op_lz_dots(st, T, nt, D, 0);
+          ProfScope ps(P, KC_LZ_ORTH, vb, st);
           op_reduce(st, IL, ni, D, RDH_LZ_H1, 0, R, 0);
           op_lz_update(st, T, nt, D, 0);
-          op_reduce(st, IL, ni, D, RDH_LZ_CHECK, 0, R, 0);
-          op_lz_dots(st, T, nt, D, 1);
-          op_reduce(st, IL, ni, D, RDH_LZ_H2, 0, R, 0);
+          op_reduce(st, IL, ni, D, RDH_LZ_CHECKH2, 0, R, 0);
           op_lz_update(st, T, nt, D, 1);
           op_reduce(st, IL, ni, D, RDH_LZ_FINAL, 0, R, 0);
           op_lz_scale(st, T, nt, D);

@@ -1026,26 +1026,60 @@ __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ili
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double *lz_basis(const InstDev &I, const InstParams &P) { return P.lz_basis ? I.V2 : I.V; }
 
-// w = G v_j with G = C + A*(y) in FP64 (pair values m64) plus the low-rank
-// term K0 D0 (K0^T v_j); partial v_j^T w is not needed (dots follow).  The
-// tile's columns and pair values are staged in LDS (as in the SpMM); teams of
-// 2^max(0, plog - 2) lanes share a row, so each lane gathers about four
-// entries of v at once.
-__global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
-                                                   int32_t from_lzv) {
+// Partial dots <V_q, w> over the rows of a tile for q < nq, w given for the
+// tile's rows in LDS: each wave takes groups of 8 basis vectors, lanes stride
+// over rows; written to partial slots 0..nq-1 of the tile.
+__device__ __forceinline__ void lz_tile_dots(const InstDev &I, const double *V, int nq, const Tile &tl,
+                                             const double *s_w, double *lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t n = I.n;
+  const int nrows = tl.row1 - tl.row0;
+  constexpr int QB = 8;
+  for (int q0 = wave * QB; q0 < nq; q0 += (BLOCK / 64) * QB) {
+    double acc[QB];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) acc[u] = 0.0;
+    for (int r = lane; r < nrows; r += 64) {
+      const double wi = s_w[r];
+      const size_t i = (size_t)tl.row0 + r;
+#pragma unroll
+      for (int u = 0; u < QB; ++u)
+        if (q0 + u < nq) acc[u] += V[(size_t)(q0 + u) * n + i] * wi;
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      const double sum = wave_sum(acc[u]);
+      if (lane == 0 && q0 + u < nq) lds[q0 + u] = sum;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += BLOCK) I.part[(size_t)q * I.prows + tl.lt] = lds[q];
+}
+
+// One Lanczos step, first half: w = G v_j with G = C + A*(y) in FP64 (pair
+// values m64) plus the low-rank term K0 D0 (K0^T v_j), partial ||w||^2, then
+// (fused) the first Gram-Schmidt dots <V_q, w>, q <= j, from the tile's w
+// kept in LDS.  The tile's columns and pair values are staged in LDS (as in
+// the SpMM); teams of 2^max(0, plog - 2) lanes share a row, so each lane
+// gathers about four entries of v at once.
+__global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__ tiles,
+                                                        const InstDev *__restrict__ insts) {
+  // staging area of the SpMV, reused for w and the dot partials afterwards
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   __shared__ int32_t s_col[TILE_MAX_ENTRIES];
   __shared__ double s_m[TILE_MAX_ENTRIES];
+  __shared__ double s_w[TILE_MAX_ROWS];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
-  if (!from_lzv && P.lz_steps <= 0) return;
-  const double *v = from_lzv ? I.lzv : lz_basis(I, P) + (size_t)P.lz_j * I.n;
+  if (P.lz_steps <= 0) return;
+  const double *V = lz_basis(I, P);
+  const double *v = V + (size_t)P.lz_j * I.n;
   double kd[LR_MAX] = {0.0, 0.0};
   for (int t = 0; t < I.r0; ++t) {
-    double s = 0.0;
-    for (int u = 0; u < I.r0; ++u) s += I.D0[t * I.r0 + u] * I.res->v[S_LZ_KV0 + u];
-    kd[t] = s;
+    double sacc = 0.0;
+    for (int u = 0; u < I.r0; ++u) sacc += I.D0[t * I.r0 + u] * I.res->v[S_LZ_KV0 + u];
+    kd[t] = sacc;
   }
   const int nrows = tl.row1 - tl.row0;
   for (int r = threadIdx.x; r <= nrows; r += BLOCK) {
@@ -1095,50 +1129,24 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv(const Tile *__restrict__ tile
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
       I.w[i] = w;
+      s_w[r] = w;
       acc[0] += w * w;
     }
   }
-  if (!from_lzv) block_partials<1, LZ_W2_SLOT>(acc, I, tl.lt);
+  block_partials<1, LZ_W2_SLOT>(acc, I, tl.lt);  // (its barrier also publishes s_w)
+  lz_tile_dots(I, V, P.lz_j + 1, tl, s_w, s_m);
 }
 
-// partial dots: q < nq: <V_q, w>; if lr: K0^T w at slots nq.. (only for the final pass)
-__global__ __launch_bounds__(BLOCK) void k_lz_dots(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
-                                                   int32_t second_pass) {
-  __shared__ double lds[(BLOCK / 64) * PSTRIDE];
-  const Tile tl = tiles[tile_index()];
-  const InstDev &I = insts[tl.inst];
-  const InstParams &P = *I.prm;
-  if (P.lz_steps <= 0 || (second_pass && P.lz_skip)) return;
-  const double *V = lz_basis(I, P);
-  const int nq = P.lz_j + 1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const size_t n = I.n;
-  // each wave takes groups of 8 basis vectors; lanes stride over rows
-  constexpr int QB = 8;
-  for (int q0 = wave * QB; q0 < nq; q0 += (BLOCK / 64) * QB) {
-    double acc[QB];
-#pragma unroll
-    for (int u = 0; u < QB; ++u) acc[u] = 0.0;
-    for (int i = tl.row0 + lane; i < tl.row1; i += 64) {
-      const double wi = I.w[i];
-#pragma unroll
-      for (int u = 0; u < QB; ++u)
-        if (q0 + u < nq) acc[u] += V[(size_t)(q0 + u) * n + i] * wi;
-    }
-#pragma unroll
-    for (int u = 0; u < QB; ++u) {
-      const double s = wave_sum(acc[u]);
-      if (lane == 0 && q0 + u < nq) lds[q0 + u] = s;
-    }
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nq; q += BLOCK) I.part[(size_t)q * I.prows + tl.lt] = lds[q];
-}
-
-// w -= sum_q V_q h_q, partial ||w||^2 and K0^T w (both passes: after the
-// first they decide whether the second is needed).
+// w -= sum_q V_q h_q with partial ||w||^2 and K0^T w.  First pass: the
+// partials go to LZ_WP_SLOT / LZ_KV_SLOT (they decide whether a second pass
+// is needed) and the second pass's dots <V_q, w'> follow from the tile's w'
+// in LDS, re-reading V from L2 right after the update read it.  Second pass
+// (skipped where the first sufficed): partials to slots 0..LR_MAX.
 __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                      int32_t final_pass) {
+  __shared__ double h[KMAX + 1];
+  __shared__ double s_w[TILE_MAX_ROWS];
+  __shared__ double lds[(BLOCK / 64) * PSTRIDE];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
@@ -1146,7 +1154,6 @@ __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ ti
   const double *V = lz_basis(I, P);
   const int nq = P.lz_j + 1;
   const size_t n = I.n;
-  __shared__ double h[KMAX + 1];
   for (int q = threadIdx.x; q < nq; q += BLOCK) h[q] = I.hcoef[q];
   __syncthreads();
   double acc[1 + LR_MAX] = {0.0, 0.0, 0.0};
@@ -1154,10 +1161,19 @@ __global__ __launch_bounds__(BLOCK) void k_lz_update(const Tile *__restrict__ ti
     double wi = I.w[i];
     for (int q = 0; q < nq; ++q) wi -= V[(size_t)q * n + i] * h[q];
     I.w[i] = wi;
+    s_w[i - tl.row0] = wi;
     acc[0] += wi * wi;
     for (int t = 0; t < I.r0; ++t) acc[1 + t] += I.K064[(size_t)i * I.r0 + t] * wi;
   }
-  block_partials<1 + LR_MAX>(acc, I, tl.lt);
+  if (final_pass) {
+    block_partials<1 + LR_MAX>(acc, I, tl.lt);
+  } else {
+    double a0[1] = {acc[0]};
+    double akv[LR_MAX] = {acc[1], acc[2]};
+    block_partials<1, LZ_WP_SLOT>(a0, I, tl.lt);
+    block_partials<LR_MAX, LZ_KV_SLOT>(akv, I, tl.lt);  // (its barrier also publishes s_w)
+    lz_tile_dots(I, V, nq, tl, s_w, lds);
+  }
 }
 
 // v_{j+1} = w / beta_j (beta from the reduce kernel)
@@ -1251,7 +1267,8 @@ enum RedOp : int {
   RD_NORM,         // ||.||^2 of a pack / copy
   RD_GEN_EXTRA,    // general mode: add constraint-major p^T r, ||r||^2 rows
   RD_GRAM,         // sum gram partials
-  RD_LZ_CHECK      // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2)
+  RD_LZ_CHECKH2    // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2),
+                   // else h2 -> hcoef, H column += h2
 };
 
 struct RedArgs {
@@ -1327,7 +1344,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
   double *res = I.res->v;
   const int nt = I.ntiles;
   const int tid = threadIdx.x;
-  if (blockIdx.y > 0 && a.op != RD_LZ_H1 && a.op != RD_LZ_H2 && a.op != RD_GRAM) return;
+  if (blockIdx.y > 0 && a.op != RD_LZ_H1 && a.op != RD_LZ_CHECKH2 && a.op != RD_GRAM) return;
   switch (a.op) {
     case RD_COMBO:
     case RD_NORM:
@@ -1394,19 +1411,16 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       break;
     }
     case RD_LZ_START:
-    case RD_LZ_CHECK:
     case RD_LZ_FINAL: {
       // (P.lz_skip and P.lz_steps are read by every thread before the
       // barriers in reduce_slots; thread 0 writes them after)
       if (a.op != RD_LZ_START && P.lz_steps <= 0) break;
-      if (a.op == RD_LZ_FINAL && P.lz_skip) break;  // done by RD_LZ_CHECK
-      reduce_slots(I, 0, 1 + I.r0, 0, nt, S);
-      if (a.op == RD_LZ_CHECK) {
-        // DGKS criterion: one classical Gram-Schmidt pass suffices unless it
-        // removed most of w (cancellation), eta = 1 / sqrt(2)
-        const bool skip = 2.0 * S[0] >= res[S_LZ_W2];
-        if (tid == 0) P.lz_skip = skip ? 1 : 0;
-        if (!skip) break;
+      if (a.op == RD_LZ_FINAL && P.lz_skip) {
+        // one pass sufficed: beta and K0^T w from the first pass's partials
+        reduce_slots(I, LZ_WP_SLOT, LZ_WP_SLOT + 1, 0, nt, S);
+        reduce_slots(I, LZ_KV_SLOT, LZ_KV_SLOT + I.r0, 0, nt, S + 1);
+      } else {
+        reduce_slots(I, 0, 1 + I.r0, 0, nt, S);
       }
       if (tid == 0) {
         const double b = sqrt(S[0]);
@@ -1424,10 +1438,18 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       break;
     }
     case RD_LZ_H1:
-    case RD_LZ_H2: {
+    case RD_LZ_CHECKH2: {
       // slots split over blockIdx.y in runs of RQ (independent coefficients)
-      if (P.lz_steps <= 0 || (a.op == RD_LZ_H2 && P.lz_skip)) break;
+      if (P.lz_steps <= 0) break;
       const int nq = P.lz_j + 1;
+      if (a.op == RD_LZ_CHECKH2) {
+        // DGKS criterion (every block decides alike): one classical
+        // Gram-Schmidt pass suffices unless it removed most of w, eta = 1/sqrt(2)
+        reduce_slots(I, LZ_WP_SLOT, LZ_WP_SLOT + 1, 0, nt, E);
+        const bool skip = 2.0 * E[0] >= res[S_LZ_W2];
+        if (blockIdx.y == 0 && tid == 0) P.lz_skip = skip ? 1 : 0;
+        if (skip) break;
+      }
       if (a.op == RD_LZ_H1 && blockIdx.y == 0) {
         reduce_slots(I, LZ_W2_SLOT, LZ_W2_SLOT + 1, 0, nt, E);
         if (tid == 0) res[S_LZ_W2] = E[0];
@@ -1726,7 +1748,7 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   if (ni <= 0) return;
   RedArgs a{op, zsel, R, extra};
   int ny = 1;
-  if (op == RD_LZ_H1 || op == RD_LZ_H2) ny = (KMAX + 1 + RQ - 1) / RQ;
+  if (op == RD_LZ_H1 || op == RD_LZ_CHECKH2) ny = (KMAX + 1 + RQ - 1) / RQ;
   else if (op == RD_GRAM) ny = (R * R + 63) / 64;
   hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
@@ -1736,11 +1758,8 @@ void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
 void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_first, dim3(nt), dim3(BLOCK), 0, s, t, d);
 }
-void op_lz_spmv(hipStream_t s, const Tile *t, int nt, const InstDev *d, int from_lzv) {
-  if (nt > 0) hipLaunchKernelGGL(k_lz_spmv, dim3(nt), dim3(BLOCK), 0, s, t, d, from_lzv);
-}
-void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d, int second_pass) {
-  if (nt > 0) hipLaunchKernelGGL(k_lz_dots, dim3(nt), dim3(BLOCK), 0, s, t, d, second_pass);
+void op_lz_spmv_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+  if (nt > 0) hipLaunchKernelGGL(k_lz_spmv_dots, dim3(nt), dim3(BLOCK), 0, s, t, d);
 }
 void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int final_pass) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_update, dim3(nt), dim3(BLOCK), 0, s, t, d, final_pass);

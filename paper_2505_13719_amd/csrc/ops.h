@@ -10,7 +10,7 @@ enum SpmmModeH : int { SPM_PLAIN = 0, SPM_TRIAL = 1, SPM_AIPP = 2 };
 enum RedOpH : int {
   RDH_COMBO = 0, RDH_SDDMM_XT, RDH_TRIAL_PROJ, RDH_PROJ_DOTS, RDH_SDDMM_YP, RDH_AIPP, RDH_EVAL, RDH_LRONLY,
   RDH_LZ_START, RDH_LZ_H1, RDH_LZ_H2, RDH_LZ_FINAL, RDH_FW_DEN, RDH_SETP, RDH_NORM, RDH_GEN_EXTRA, RDH_GRAM,
-  RDH_LZ_CHECK
+  RDH_LZ_CHECKH2
 };
 
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp);
@@ -40,8 +40,7 @@ void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstD
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra);
 void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d);
-void op_lz_spmv(hipStream_t s, const Tile *t, int nt, const InstDev *d, int from_lzv);
-void op_lz_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d, int second_pass);
+void op_lz_spmv_dots(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int final_pass);
 void op_lz_scale(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_lz_combine(hipStream_t s, const Tile *t, int nt, const InstDev *d, int to_lzv);
