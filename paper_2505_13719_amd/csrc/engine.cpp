@@ -1147,11 +1147,17 @@ static Task lanczos(Ctx c, double tol_abs, int max_iter, int use_prev, EigOut &o
   int k = 0;
   out = EigOut{};
   std::vector<double> Hs, w, Q;
+  // shift of the SpMV: the latest diagonal entry of the projected matrix
+  // (a warm start begins near the previous smallest eigenvalue)
+  double sigma = S.lz_sigma;
+  int tri0 = 1;
   for (;;) {
     const int steps = std::min(8, kmax - k);
     S.prm.lz_j = k;
     S.prm.lz_j0 = k;
     S.prm.lz_steps = steps;
+    S.prm.lz_shift = sigma;
+    S.prm.lz_tri0 = tri0;
     PendingOp &op = c.op(OP_LZ_STEPS);
     op.steps = steps;
     op.dl_count = (int64_t)steps * (KMAX + 2);
@@ -1161,7 +1167,11 @@ static Task lanczos(Ctx c, double tol_abs, int max_iter, int use_prev, EigOut &o
       const double *d = S.dl.data() + (size_t)u * (KMAX + 2);
       for (int i = 0; i <= col; ++i) S.H[(size_t)col * LD + i] = d[i];
       S.H[(size_t)col * LD + col + 1] = d[KMAX + 1];
+      // undo the SpMV's shift and three-term subtraction
+      S.H[(size_t)col * LD + col] += sigma;
+      if (col >= tri0) S.H[(size_t)col * LD + col - 1] += S.H[(size_t)(col - 1) * LD + col];
     }
+    sigma = S.H[(size_t)(k + steps - 1) * LD + (k + steps - 1)];
     k += steps;
     out.iters += steps;
     S.result.n_matvec += steps;
@@ -1175,6 +1185,7 @@ static Task lanczos(Ctx c, double tol_abs, int max_iter, int use_prev, EigOut &o
     const double bk = S.H[(size_t)(k - 1) * LD + k];
     const bool breakdown = !(bk > 1e-14 * std::max(1.0, std::fabs(w[0])));
     const double res = breakdown ? 0.0 : std::fabs(bk * Q[(size_t)(k - 1) * k + 0]);
+    S.lz_sigma = w[0];
     out.lam = w[0];
     out.res = res;
     const bool conv = res <= std::max(tol_abs, c.o.eig_tol * std::max(1.0, std::fabs(w[0])));
@@ -1203,6 +1214,7 @@ static Task lanczos(Ctx c, double tol_abs, int max_iter, int use_prev, EigOut &o
         S.H[(size_t)cc * LD + qk] = bk * Q[(size_t)(k - 1) * k + cc];
       }
       k = qk;
+      tri0 = qk + 1;  // v_qk couples to every kept Ritz vector (arrowhead)
       out.restarts++;
     }
   }

@@ -131,6 +131,7 @@ struct Slot {
   bool has_op = false, done = false;
   hallar_result result{};
   std::vector<double> H;    // host Lanczos projected matrix
+  double lz_sigma = 0.0;    // SpMV shift for the next Lanczos call (last smallest Ritz value)
   std::vector<double> dl;   // downloaded block of the last round
   // buffer bookkeeping
   std::vector<int> free_bufs;

@@ -64,6 +64,8 @@ struct InstParams {
   int32_t lz_j0;        // lz_j at the start of the round (download layout)
   int32_t lz_use_prev;  // Lanczos start: previous vector + small noise
   int32_t lz_skip;      // set on the device: this step's second Gram-Schmidt pass is not needed
+  int32_t lz_tri0;      // from this basis index on, v_{j-1} is the previous vector of a three-term chain
+  double lz_shift;      // the SpMV forms (G - lz_shift I) v_j - beta_{j-1} v_{j-1}
   int32_t fw_v_on;      // Frank-Wolfe direction present (theta > 0)
   uint64_t lz_seed;     // counter-based start-vector seed
   int64_t up_off;       // offset of this instance's coefficients in the upload buffer

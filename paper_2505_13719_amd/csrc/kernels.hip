@@ -1056,8 +1056,9 @@ __device__ __forceinline__ void lz_tile_dots(const InstDev &I, const double *V, 
   for (int q = threadIdx.x; q < nq; q += BLOCK) I.part[(size_t)q * I.prows + tl.lt] = lds[q];
 }
 
-// One Lanczos step, first half: w = G v_j with G = C + A*(y) in FP64 (pair
-// values m64) plus the low-rank term K0 D0 (K0^T v_j), partial ||w||^2, then
+// One Lanczos step, first half: w = (G - s I) v_j - beta_{j-1} v_{j-1} with
+// G = C + A*(y) in FP64 (pair values m64) plus the low-rank term
+// K0 D0 (K0^T v_j) and the host's shift s, partial ||w||^2, then
 // (fused) the first Gram-Schmidt dots <V_q, w>, q <= j, from the tile's w
 // kept in LDS.  The tile's columns and pair values are staged in LDS (as in
 // the SpMM); teams of 2^max(0, plog - 2) lanes share a row, so each lane
@@ -1128,6 +1129,11 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
     for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
+      // shifted three-term form: the Gram-Schmidt dots then see only the
+      // small remainder, so the DGKS test can skip the second pass (the
+      // host adds the shift and beta back into the projected matrix)
+      w -= P.lz_shift * v[i];
+      if (P.lz_j >= P.lz_tri0) w -= I.res->v[S_LZ_BETA] * V[(size_t)(P.lz_j - 1) * I.n + i];
       I.w[i] = w;
       s_w[r] = w;
       acc[0] += w * w;
