@@ -105,7 +105,11 @@ typedef struct {
                                        keeps the fastest (see hallar_schedule); 0: the default schedule.
                                        The schedule fixes the order of the partial sums, so results of
                                        differently tuned handles agree to rounding, not bit for bit. */
-  int32_t pad_;
+  int32_t lower_gather;             /* 1: the gradient SpMM always reads the lower half's pair values
+                                       through the pair ids; 0 (default): where every strictly-lower
+                                       pair is constrained with one shared coefficient and no sparse
+                                       objective entry, it recomputes them from the factor rows and
+                                       (p_l, b_l) kept in lower order.  Both give identical bits. */
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);

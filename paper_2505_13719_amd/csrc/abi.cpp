@@ -43,6 +43,7 @@ bool check_opts(const hallar_options &o, std::string &msg) {
   if (!(o.lam0 > 0)) { msg = "opts.lam0 must be > 0"; return false; }
   if (o.rank_cap < 0 || o.rank_cap > hl::R_MAX) { msg = "opts.rank_cap must be in [0, 64]"; return false; }
   if (o.eig_kmax < 0 || o.eig_kmax > hl::KMAX) { msg = "opts.eig_kmax must be in [0, 64]"; return false; }
+  if (o.lower_gather != 0 && o.lower_gather != 1) { msg = "opts.lower_gather must be 0 or 1"; return false; }
   if (o.fista_max_iter < 1 || o.aipp_max_iter < 1 || o.hlr_max_iter < 1 || o.outer_max_iter < 1 || o.eig_max_iter < 1) {
     msg = "iteration caps must be >= 1";
     return false;
@@ -405,6 +406,7 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     v->hp.nlower = src.hp.nlower;
     v->hp.nentries = src.hp.nentries;
     v->hp.direct = src.hp.direct;
+    v->hp.low_recompute = src.hp.low_recompute;
     v->hp.has_c = src.hp.has_c;
     v->hp.r0 = src.hp.r0;
     v->hp.b_l1 = src.hp.b_l1;

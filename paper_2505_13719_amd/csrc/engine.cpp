@@ -158,7 +158,7 @@ struct Carve {
 };
 
 struct Layout {
-  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, b, K0, K064, D0, c_diag;
+  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, low_pb, b, K0, K064, D0, c_diag;
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, gram, tiles, ilist;
   size_t total;
@@ -183,6 +183,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.rowptr_l = c.take((n + 1) * 4);
   L.col_l = c.take(nl * 4);
   L.pid_l = c.take(nl * 4);
+  L.low_pb = c.take(hp.low_recompute ? nl * 16 : 0);
   L.b = c.take(m * 8);
   L.c_diag = c.take(hp.c_diag_only ? n * 8 : 0);
   L.K0 = c.take(n * hp.r0 * sz);
@@ -318,6 +319,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   Slot &S = *sl;
   S.hp = std::move(hp);
   HostProblem &h = S.hp;
+  if (P.opts.lower_gather) h.low_recompute = false;
   S.Rcap = rcap_for(P.opts, P.prec);
   S.kmax = kmax_for(P.opts, h.n);
   const Layout L = make_layout(h, P.prec, S.Rcap, S.kmax);
@@ -411,6 +413,8 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.rowptr_l = (const int32_t *)at(L.rowptr_l);
   D.col_l = (const int32_t *)at(L.col_l);
   D.pid_l = (const int32_t *)at(L.pid_l);
+  D.low_mode = h.low_recompute ? 1 : 0;
+  D.low_pb = h.low_recompute ? (double *)at(L.low_pb) : nullptr;
   D.K0 = at(L.K0);
   D.K064 = (const double *)at(L.K064);
   D.D0 = (const double *)at(L.D0);
@@ -545,7 +549,8 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
     b.sddmm += n * R * sz + (n + 1) * 4 + Pp * (4 + (h.direct ? 4 + (h.pa_uniform ? 0 : sz) : 0) +
                                                  (h.has_c && !h.c_diag_only ? sz : 0)) +
                (h.c_diag_only ? 8 * n : 0) + 16 * m;
-    b.spmm_core += n * R * sz + 2 * (n + 1) * 4 + Pp * (4 + sz) + nl * 8;
+    // lower half: column and pair id, or column and (p_l, b_l) when recomputed
+    b.spmm_core += n * R * sz + 2 * (n + 1) * 4 + Pp * (4 + sz) + nl * (h.low_recompute ? 20 : 8);
     b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 8 + 2 * (n + 1) * 4;
     b.vec_n8 += n * 8;
   }
@@ -569,10 +574,13 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   const double sz = prec == 0 ? 8.0 : 4.0;
   double msum = 0, psum = 0;
   bool any_lr = false;
+  int64_t maxnl_low = 0;
   for (int s : g.slots) {
-    msum += P.slots[s]->hp.m;
-    psum += (double)P.slots[s]->hp.npairs;
-    any_lr = any_lr || P.slots[s]->hp.r0 > 0;
+    const HostProblem &h = P.slots[s]->hp;
+    msum += h.m;
+    psum += (double)h.npairs;
+    any_lr = any_lr || h.r0 > 0;
+    if (h.low_recompute) maxnl_low = std::max<int64_t>(maxnl_low, h.nlower);
   }
   auto red = [&](int op, int zsel) {
     ProfScope ps(P, KC_REDUCE, 0.0, st);
@@ -629,8 +637,11 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       break;
     case OP_PACK:
       {
+        // the solve's first op: U0, and the caller's dual start p copied into
+        // the lower-order pair operands
         ProfScope ps(P, KC_OTHER, 0.0, st);
         op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
+        if (maxnl_low > 0) op_low_pb(st, IL, ni, maxnl_low, D);
       }
       red(RDH_NORM, 0);
       break;
@@ -707,6 +718,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       {
         ProfScope ps(P, KC_VEC, 0.0, st);
         op_set_p(st, IL, ni, g.maxm, D);
+        if (maxnl_low > 0) op_low_pb(st, IL, ni, maxnl_low, D);
       }
       red(RDH_SETP, 0);
       break;

@@ -27,6 +27,10 @@ struct HostProblem {
   double pa_const = 0.0;
   bool c_diag_only = false;     // C's sparse part is diagonal: c_diag[i] = C_ii
   std::vector<double> c_diag;
+  // every strictly-lower pair is constrained with coefficient pa_const and
+  // has no sparse objective entry: the gradient SpMM recomputes the lower
+  // half's values from (p_l, b_l) kept in lower order
+  bool low_recompute = false;
   // general mode (a constraint with several pairs or a pair in several constraints)
   std::vector<int32_t> eptr, econ, cptr, cent, epair;
   std::vector<double> ea, ew;

@@ -100,6 +100,12 @@ struct InstDev {
   // structure (device)
   const int32_t *rowptr_u, *col_u, *pcon;   // upper CSR over S (pair k = position), constraint of pair (0 = none)
   const int32_t *rowptr_l, *col_l, *pid_l;  // strictly-lower transpose of S with pair ids
+  // lower-half recompute: every strictly-lower pair is constrained, with the
+  // shared coefficient pa_const and no sparse objective entry, so the
+  // gradient SpMM forms its values from (p_l, b_l) stored in lower order
+  // instead of gathering the SDDMM's values through pid_l
+  int32_t low_mode;
+  double *low_pb;                           // nlower x {p_l, b_l} when low_mode
   const void *c_u, *pa;                     // operator type: C_ij per pair, (A_l)_ij of the pair's constraint
   int32_t pa_uniform, c_diag_only;          // the SDDMM reads pa_const / c_diag instead of pa / c_u
   double pa_const;

@@ -47,6 +47,39 @@ __device__ __forceinline__ T group_sum(T v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
+// <U_i, U_j> of one pair over one 16-byte chunk of each row: FP64 fused
+// multiply-adds from zero.  A pair's product is the per-chunk partials
+// combined in the xor-butterfly order of group_sum (chunk 0 alone for one
+// chunk, d0 + d1 for two), whether one thread holds both chunks (the narrow
+// SDDMM) or one lane per chunk does (the wide SDDMM and the SpMM), so every
+// kernel that forms a pair value gets the same bits.
+template <typename T>
+__device__ __forceinline__ double chunk_dot(const Chunk<T> &a, const Chunk<T> &b) {
+  double d = 0.0;
+#pragma unroll
+  for (int e = 0; e < NCh<T>::N; ++e) d = fma((double)a.v[e], (double)b.v[e], d);
+  return d;
+}
+
+// Augmented-Lagrangian terms of one constrained pair (Section 3: the
+// multiplier estimate inside the gradient of the augmented Lagrangian):
+// t = (2 - delta_ij) a B, r = t - b_l, y' = p_l + beta r and the pair value
+// m = c + a y'.  Contraction is off and the fused steps are explicit, so the
+// SDDMM and the SpMM's recomputed lower half round alike.
+struct PairAL {
+  double t, r, y, m;
+};
+__device__ __forceinline__ PairAL pair_al(double cv, double av, double bl, double pl, double beta, double B,
+                                          double w2) {
+#pragma clang fp contract(off)
+  PairAL o;
+  o.t = w2 * av * B;
+  o.r = o.t - bl;
+  o.y = fma(beta, o.r, pl);
+  o.m = fma(av, o.y, cv);
+  return o;
+}
+
 // Block reduction of NQ doubles per thread into partial row `row` of the
 // instance (slot q at part[q * prows + row]).
 template <int NQ, int BASE = 0>
@@ -174,25 +207,20 @@ __device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, con
       const int k = kk[u];
       if (k >= kend) continue;
       // FP64 accumulation of the FP32 / FP64 products
-      double B = 0.0;
-#pragma unroll
-      for (int c = 0; c < G; ++c)
-#pragma unroll
-        for (int e = 0; e < NC; ++e) B += (double)ci[u][c].v[e] * (double)cj[u][c].v[e];
+      double B = chunk_dot(ci[u][0], cj[u][0]);
+      if constexpr (G == 2) B = B + chunk_dot(ci[u][1], cj[u][1]);
       const double w2 = ii[u] == jj[u] ? 1.0 : 2.0;
       acc[0] += w2 * cv[u] * B;
       if (direct) {
         double mv = cv[u];
         if (l[u] > 0) {
-          const double t = w2 * av[u] * B;
-          const double r = t - bl[u];
-          const double y = pl[u] + beta * r;
-          acc[1] += pl[u] * r;
-          acc[2] += r * r;
-          acc[3] += y * t;
-          if (a.write_T) I.TY[l[u] - 1] = t;
-          if (a.write_yp) I.yp[l[u] - 1] = y;
-          mv = cv[u] + av[u] * y;
+          const PairAL q = pair_al(cv[u], av[u], bl[u], pl[u], beta, B, w2);
+          acc[1] += pl[u] * q.r;
+          acc[2] += q.r * q.r;
+          acc[3] += q.y * q.t;
+          if (a.write_T) I.TY[l[u] - 1] = q.t;
+          if (a.write_yp) I.yp[l[u] - 1] = q.y;
+          mv = q.m;
         }
         if (mout) mout[k] = (T)mv;
       } else {
@@ -293,9 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
       for (int u = 0; u < UN; ++u) {
         // products accumulate in FP64 (also for FP32 U): the AL value that the
         // FISTA / AIPP tests compare must be exact for the stored iterate
-        double d = 0.0;
-#pragma unroll
-        for (int e = 0; e < NC; ++e) d += (double)ci[u].v[e] * (double)cj[u].v[e];
+        double d = chunk_dot(ci[u], cj[u]);
         d = group_sum<G>(d);
         const int pb = (ps + u) * PPP + grp;
         if (ch == 0 && pb < nb) s_d[pb] = d;
@@ -312,15 +338,13 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
       if (direct) {
         double mv = cv[u];
         if (l[u] > 0) {
-          const double t = w2 * av[u] * B;
-          const double r = t - bl[u];
-          const double y = pl[u] + beta * r;
-          acc[1] += pl[u] * r;
-          acc[2] += r * r;
-          acc[3] += y * t;
-          if (a.write_T) I.TY[l[u] - 1] = t;
-          if (a.write_yp) I.yp[l[u] - 1] = y;
-          mv = cv[u] + av[u] * y;
+          const PairAL q = pair_al(cv[u], av[u], bl[u], pl[u], beta, B, w2);
+          acc[1] += pl[u] * q.r;
+          acc[2] += q.r * q.r;
+          acc[3] += q.y * q.t;
+          if (a.write_T) I.TY[l[u] - 1] = q.t;
+          if (a.write_yp) I.yp[l[u] - 1] = q.y;
+          mv = q.m;
         }
         if (mout) mout[k] = (T)mv;
       } else {
@@ -473,11 +497,12 @@ struct SpmmArgs {
 
 // Stage a tile's entries of S u S^T into LDS: columns and pair values of the
 // upper CSR (coalesced), then the lower transpose, whose values are gathered
-// through the pair ids; SU entries per thread are loaded before any is
-// stored, so the gathers of a thread are in flight together.
+// through the pair ids unless the caller recomputes them (lower_vals false:
+// columns only); SU entries per thread are loaded before any is stored, so
+// the gathers of a thread are in flight together.
 template <typename T>
 __device__ __forceinline__ void stage_entries(const InstDev &I, const T *__restrict__ m, int ku0, int nu, int kl0,
-                                              int nl, int32_t *s_col, T *s_m) {
+                                              int nl, bool lower_vals, int32_t *s_col, T *s_m) {
   constexpr int SU = 8;
   for (int e0 = threadIdx.x; e0 < nu; e0 += BLOCK * SU) {
     int c[SU];
@@ -507,13 +532,14 @@ __device__ __forceinline__ void stage_entries(const InstDev &I, const T *__restr
       const int e = e0 + u * BLOCK;
       if (e < nl) {
         c[u] = I.col_l[kl0 + e];
-        id[u] = I.pid_l[kl0 + e];
+        if (lower_vals) id[u] = I.pid_l[kl0 + e];
       }
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int e = e0 + u * BLOCK;
-      if (e < nl) v[u] = m[id[u]];
+      v[u] = T(0);
+      if (lower_vals && e < nl) v[u] = m[id[u]];
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
@@ -622,9 +648,19 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
   if (nu + nl <= TILE_MAX_ENTRIES) {
+    // The gradient SpMMs follow an SDDMM on the same factor, dual iterate and
+    // penalty.  Where every lower pair is a constrained pair with the shared
+    // coefficient and no sparse objective entry, a lower entry's value is
+    // recomputed from the two factor rows (the neighbour row is gathered for
+    // the product anyway) and (p_l, b_l) read in lower order, with the
+    // SDDMM's arithmetic: no gather of the SDDMM's values through the pair
+    // ids, which would cost a cache line per 4- or 8-byte value.
+    const bool rec = MODE != SP_PLAIN && I.low_mode != 0;
     // stage the tile's columns and pair values of S u S^T (upper part, then
     // the lower transpose through its pair ids) with coalesced loads
-    stage_entries<T>(I, m, ku0, nu, kl0, nl, s_col, s_m);
+    stage_entries<T>(I, m, ku0, nu, kl0, nl, !rec, s_col, s_m);
+    const double beta = P.beta, a_low = I.pa_const;
+    const double2 *__restrict__ low_pb = reinterpret_cast<const double2 *>(I.low_pb);
     // a team of G * S lanes per row: S pair streams (power of two) when the
     // tile has fewer rows than the block has G-lane groups (long rows)
     int S = 1;
@@ -641,6 +677,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
       if (strm == 0) in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
       const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
       const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
+      // own row (chunk ch) and the row's (p_l, b_l) for recomputed values
+      Chunk<T> xo;
+      if (rec && cnt > cu) xo = ldc(X + (size_t)i * R + ch * NC);
+      const double2 *__restrict__ pbr = rec ? low_pb + (s_rl[r] - cu) : nullptr;
       // FP64 accumulation (also for FP32 data): near a stationary point the
       // row sum cancels, and the FISTA / AIPP tests need the gradient to
       // relative accuracy, not to the size of its terms
@@ -650,17 +690,31 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
       for (int q = strm * UN; q < cnt; q += S * UN) {
         Chunk<T> x[UN];
         double mv[UN];
+        double2 pb[UN];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
           const int idx = q + u;
           if (idx < cnt) {
             const int pos = idx < cu ? a0 + idx : b0 + idx;
-            mv[u] = (double)s_m[pos];
+            if (rec && idx >= cu) pb[u] = pbr[idx];
+            else mv[u] = (double)s_m[pos];
             x[u] = ldc(X + (size_t)s_col[pos] * R + ch * NC);
           } else {
             mv[u] = 0.0;
 #pragma unroll
             for (int e = 0; e < NC; ++e) x[u].v[e] = T(0);
+          }
+        }
+        if (rec) {
+          // lanes of a G-group share idx, so the butterfly stays inside
+          // lanes that take this branch together
+#pragma unroll
+          for (int u = 0; u < UN; ++u) {
+            const int idx = q + u;
+            if (idx >= cu && idx < cnt) {
+              const double B = group_sum<G>(chunk_dot(x[u], xo));
+              mv[u] = (double)(T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
+            }
           }
         }
 #pragma unroll
@@ -1021,6 +1075,19 @@ __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ili
   if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I, I.ntiles + blockIdx.x);
 }
 
+// (p_l, b_l) of every strictly-lower pair in lower order, for the gradient
+// SpMM's recomputed lower half; rerun whenever p changes (instances without
+// the recompute return at once).
+__global__ __launch_bounds__(BLOCK) void k_low_pb(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  if (!I.low_mode) return;
+  double2 *out = reinterpret_cast<double2 *>(I.low_pb);
+  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < I.nlower; e += gridDim.x * BLOCK) {
+    const int l = I.pcon[I.pid_l[e]];  // >= 1: every lower pair is constrained in this mode
+    out[e] = make_double2(I.p[l - 1], I.b[l - 1]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Lanczos (FP64).  Basis rows V[q * n + i]; w is the work vector.
 // ---------------------------------------------------------------------------
@@ -1091,7 +1158,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
   const int ku0 = s_ru[0], nu = s_ru[nrows] - ku0;
   const int kl0 = s_rl[0], nl = s_rl[nrows] - kl0;
   const bool staged = nu + nl <= TILE_MAX_ENTRIES;
-  if (staged) stage_entries<double>(I, I.m64, ku0, nu, kl0, nl, s_col, s_m);
+  if (staged) stage_entries<double>(I, I.m64, ku0, nu, kl0, nl, true, s_col, s_m);
   const int plog = staged ? max(0, (int)tl.plog_s - 2) : (int)tl.plog_s;
   const int TS = 1 << plog;
   const int team = threadIdx.x >> plog;
@@ -1749,6 +1816,12 @@ void op_fw_den_gen(hipStream_t s, const int32_t *ilist, int ni, int maxm, const 
 void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d) {
   if (ni <= 0 || maxm <= 0) return;
   hipLaunchKernelGGL(k_set_p, dim3((maxm + BLOCK - 1) / BLOCK, ni), dim3(BLOCK), 0, s, ilist, d);
+}
+void op_low_pb(hipStream_t s, const int32_t *ilist, int ni, int64_t maxnl, const InstDev *d) {
+  if (ni <= 0 || maxnl <= 0) return;
+  const int64_t nb = (maxnl + BLOCK - 1) / BLOCK;
+  const int gx = nb < 4096 ? (int)nb : 4096;
+  hipLaunchKernelGGL(k_low_pb, dim3(gx, ni), dim3(BLOCK), 0, s, ilist, d);
 }
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra) {
   if (ni <= 0) return;

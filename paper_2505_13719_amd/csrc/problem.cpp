@@ -197,6 +197,12 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
         }
       }
   }
+  {
+    bool low = direct && hp.pa_uniform && (!has_c || hp.c_diag_only) && nl > 0;
+    for (int64_t e = 0; e < nl && low; ++e)
+      if (hp.pcon[hp.pid_l[e]] <= 0) low = false;
+    hp.low_recompute = low;
+  }
   // low-rank part (objective only)
   if (p->n_lowrank < 0) return "n_lowrank < 0";
   if (p->n_lowrank > 1) {

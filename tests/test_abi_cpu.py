@@ -35,6 +35,8 @@ def test_default_options_match_oracle_readings():
     for k in ("eps", "beta1", "beta_growth", "beta_max", "infeas_ratio", "pinf_gate", "stall_ratio", "stall_growth", "eps1", "eps_floor",
               "eps_decay", "sigma", "chi", "lam0", "drop_tol", "eig_frac"):
         assert getattr(o, k) == pytest.approx(getattr(ref, k)), k
+    # library-only switches: default schedule, lower half recomputed where eligible
+    assert o.autotune == 0 and o.lower_gather == 0
 
 
 def _bad(prob, code):

@@ -175,3 +175,41 @@ def test_autotuned_schedule_solves_alike():
     for r in res.values():
         assert r["status"] == "ok", r
     assert abs(res[0]["pval"] - res[1]["pval"]) <= 1e-5 * (1 + abs(res[0]["pval"]))
+
+
+LOWER_CASES = [
+    ("mc_300x400", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP32_MIXED, 1),
+    ("mc_300x400_fp64", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP64, 1),
+    ("theta_er150", lambda: _make("theta_er150", None), H.FP64, 1),
+    # a 12-column start: 16-column FP32 rows, four lanes per row (butterfly dots)
+    ("mc_wide_fp32", lambda: si.mc_planted(200, 300, 6, 15000, seed=9), H.FP32_MIXED, 12),
+]
+
+
+@pytest.mark.parametrize("name,maker,prec,r0", LOWER_CASES, ids=[c[0] for c in LOWER_CASES])
+def test_lower_recompute_bitwise(name, maker, prec, r0):
+    """The gradient SpMM's lower half recomputed from the factor rows and
+    (p_l, b_l) in lower order (opts.lower_gather = 0) takes the SDDMM's
+    arithmetic, so the whole solve is bit-identical to the one that gathers
+    the SDDMM's pair values (lower_gather = 1).  The SpMM's algorithmic bytes
+    tell the two paths apart (column + (p_l, b_l) vs column + pair id)."""
+    d = dev()
+    prob = maker()
+    out = {}
+    for lg in (1, 0):
+        h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, lower_gather=lg))
+        try:
+            U_0 = np.random.default_rng(7).standard_normal((prob.n, r0))
+            res = H.hallar_solve(h, torch.tensor(U_0, device=d))
+            U = torch.empty((prob.n, max(res["rank"], 1)), dtype=torch.float64, device=d)
+            p = torch.empty(max(prob.m, 1), dtype=torch.float64, device=d)
+            H.hallar_get_solution(h, U, p)
+            out[lg] = (res, U.cpu().numpy(), p.cpu().numpy(), H.hallar_profile(h))
+        finally:
+            H.hallar_destroy(h)
+    (r1, U1, p1, f1), (r0, U0, p0, f0) = out[1], out[0]
+    assert r0["status"] == "ok", r0
+    for k in ("pval", "dval", "gap", "pinf", "rank", "outer_iters", "n_fista_trials", "n_spmm", "n_hlr_iters"):
+        assert r0[k] == r1[k], (k, r0[k], r1[k])
+    assert np.array_equal(U0, U1) and np.array_equal(p0, p1)
+    assert f0["spmm"]["bytes"] != f1["spmm"]["bytes"]
