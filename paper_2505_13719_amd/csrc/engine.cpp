@@ -158,7 +158,7 @@ struct Carve {
 };
 
 struct Layout {
-  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, low_pb, b, K0, K064, D0, c_diag;
+  size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, low_pb, upb, b, K0, K064, D0, c_diag;
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, gram, tiles, ilist;
   size_t total;
@@ -184,6 +184,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.col_l = c.take(nl * 4);
   L.pid_l = c.take(nl * 4);
   L.low_pb = c.take(hp.low_recompute ? nl * 16 : 0);
+  L.upb = c.take(hp.direct ? P * 16 : 0);
   L.b = c.take(m * 8);
   L.c_diag = c.take(hp.c_diag_only ? n * 8 : 0);
   L.K0 = c.take(n * hp.r0 * sz);
@@ -415,6 +416,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.pid_l = (const int32_t *)at(L.pid_l);
   D.low_mode = h.low_recompute ? 1 : 0;
   D.low_pb = h.low_recompute ? (double *)at(L.low_pb) : nullptr;
+  D.upb = h.direct ? (double *)at(L.upb) : nullptr;
   D.K0 = at(L.K0);
   D.K064 = (const double *)at(L.K064);
   D.D0 = (const double *)at(L.D0);
@@ -574,13 +576,14 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   const double sz = prec == 0 ? 8.0 : 4.0;
   double msum = 0, psum = 0;
   bool any_lr = false;
-  int64_t maxnl_low = 0;
+  int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
   for (int s : g.slots) {
     const HostProblem &h = P.slots[s]->hp;
     msum += h.m;
     psum += (double)h.npairs;
     any_lr = any_lr || h.r0 > 0;
-    if (h.low_recompute) maxnl_low = std::max<int64_t>(maxnl_low, h.nlower);
+    if (h.direct) max_pb = std::max<int64_t>(max_pb, h.npairs);
+    if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
   }
   auto red = [&](int op, int zsel) {
     ProfScope ps(P, KC_REDUCE, 0.0, st);
@@ -638,10 +641,10 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     case OP_PACK:
       {
         // the solve's first op: U0, and the caller's dual start p copied into
-        // the lower-order pair operands
+        // the pair-order and lower-order {p_l, b_l} operands
         ProfScope ps(P, KC_OTHER, 0.0, st);
         op_pack_f64(prec, R, st, T, nt, D, o.ext, o.ext_r, o.ext_ld, o.dst, 1.0);
-        if (maxnl_low > 0) op_low_pb(st, IL, ni, maxnl_low, D);
+        if (max_pb > 0) op_refresh_pb(st, IL, ni, max_pb, D);
       }
       red(RDH_NORM, 0);
       break;
@@ -718,7 +721,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       {
         ProfScope ps(P, KC_VEC, 0.0, st);
         op_set_p(st, IL, ni, g.maxm, D);
-        if (maxnl_low > 0) op_low_pb(st, IL, ni, maxnl_low, D);
+        if (max_pb > 0) op_refresh_pb(st, IL, ni, max_pb, D);
       }
       red(RDH_SETP, 0);
       break;
@@ -1571,6 +1574,8 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
   const int32_t *IL = slot_ilist(P, s);
   const InstDev *D = P.d_insts;
   op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  // the SDDMM reads {p_l, b_l} in pair order: bring them up to date with p
+  if (S.hp.direct) op_refresh_pb(st, IL, 1, std::max<int64_t>(S.hp.npairs, S.hp.low_recompute ? S.hp.nlower : 0), D);
   op_lr_dots(P.prec, R, st, T_, nt, D, RU);
   op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0);
   if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);

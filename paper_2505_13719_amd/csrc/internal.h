@@ -106,6 +106,10 @@ struct InstDev {
   // instead of gathering the SDDMM's values through pid_l
   int32_t low_mode;
   double *low_pb;                           // nlower x {p_l, b_l} when low_mode
+  // direct mode: {p_l, b_l} of each pair's constraint in pair order (zeros
+  // for unconstrained pairs), so the SDDMM's loads of them do not wait for
+  // the load of the pair's constraint id
+  double *upb;
   const void *c_u, *pa;                     // operator type: C_ij per pair, (A_l)_ij of the pair's constraint
   int32_t pa_uniform, c_diag_only;          // the SDDMM reads pa_const / c_diag instead of pa / c_u
   double pa_const;

@@ -189,10 +189,11 @@ __device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, con
         else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
           l[u] = I.pcon[k];
+          const double2 v = reinterpret_cast<const double2 *>(I.upb)[k];
           if (l[u] > 0) {
             av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
-            bl[u] = I.b[l[u] - 1];
-            pl[u] = I.p[l[u] - 1];
+            bl[u] = v.y;
+            pl[u] = v.x;
           }
         }
       }
@@ -294,10 +295,11 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
         else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
           l[u] = I.pcon[k];
+          const double2 v = reinterpret_cast<const double2 *>(I.upb)[k];
           if (l[u] > 0) {
             av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
-            bl[u] = I.b[l[u] - 1];
-            pl[u] = I.p[l[u] - 1];
+            bl[u] = v.y;
+            pl[u] = v.x;
           }
         }
       }
@@ -689,7 +691,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
       for (int e = 0; e < NC; ++e) w[e] = 0.0;
       for (int q = strm * UN; q < cnt; q += S * UN) {
         Chunk<T> x[UN];
-        double mv[UN];
+        T mv[UN];
         double2 pb[UN];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
@@ -697,10 +699,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
           if (idx < cnt) {
             const int pos = idx < cu ? a0 + idx : b0 + idx;
             if (rec && idx >= cu) pb[u] = pbr[idx];
-            else mv[u] = (double)s_m[pos];
+            else mv[u] = s_m[pos];
             x[u] = ldc(X + (size_t)s_col[pos] * R + ch * NC);
           } else {
-            mv[u] = 0.0;
+            mv[u] = T(0);
 #pragma unroll
             for (int e = 0; e < NC; ++e) x[u].v[e] = T(0);
           }
@@ -713,14 +715,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
             const int idx = q + u;
             if (idx >= cu && idx < cnt) {
               const double B = group_sum<G>(chunk_dot(x[u], xo));
-              mv[u] = (double)(T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
+              mv[u] = (T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
             }
           }
         }
 #pragma unroll
         for (int u = 0; u < UN; ++u)
 #pragma unroll
-          for (int e = 0; e < NC; ++e) w[e] += mv[u] * (double)x[u].v[e];
+          for (int e = 0; e < NC; ++e) w[e] += (double)mv[u] * (double)x[u].v[e];
       }
       for (int o = TS / 2; o >= G; o >>= 1) {
 #pragma unroll
@@ -1075,16 +1077,25 @@ __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ili
   if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I, I.ntiles + blockIdx.x);
 }
 
-// (p_l, b_l) of every strictly-lower pair in lower order, for the gradient
-// SpMM's recomputed lower half; rerun whenever p changes (instances without
-// the recompute return at once).
-__global__ __launch_bounds__(BLOCK) void k_low_pb(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts) {
+// {p_l, b_l} per pair in pair order (direct mode, zeros for unconstrained
+// pairs) for the SDDMM, and per strictly-lower pair in lower order for the
+// gradient SpMM's recomputed lower half; rerun whenever p changes.
+__global__ __launch_bounds__(BLOCK) void k_refresh_pb(const int32_t *__restrict__ ilist,
+                                                      const InstDev *__restrict__ insts) {
   const InstDev &I = insts[ilist[blockIdx.y]];
-  if (!I.low_mode) return;
-  double2 *out = reinterpret_cast<double2 *>(I.low_pb);
-  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < I.nlower; e += gridDim.x * BLOCK) {
-    const int l = I.pcon[I.pid_l[e]];  // >= 1: every lower pair is constrained in this mode
-    out[e] = make_double2(I.p[l - 1], I.b[l - 1]);
+  if (I.upb) {
+    double2 *out = reinterpret_cast<double2 *>(I.upb);
+    for (int k = blockIdx.x * BLOCK + threadIdx.x; k < I.npairs; k += gridDim.x * BLOCK) {
+      const int l = I.pcon[k];
+      out[k] = l > 0 ? make_double2(I.p[l - 1], I.b[l - 1]) : make_double2(0.0, 0.0);
+    }
+  }
+  if (I.low_mode) {
+    double2 *out = reinterpret_cast<double2 *>(I.low_pb);
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < I.nlower; e += gridDim.x * BLOCK) {
+      const int l = I.pcon[I.pid_l[e]];  // >= 1: every lower pair is constrained in this mode
+      out[e] = make_double2(I.p[l - 1], I.b[l - 1]);
+    }
   }
 }
 
@@ -1817,11 +1828,11 @@ void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstD
   if (ni <= 0 || maxm <= 0) return;
   hipLaunchKernelGGL(k_set_p, dim3((maxm + BLOCK - 1) / BLOCK, ni), dim3(BLOCK), 0, s, ilist, d);
 }
-void op_low_pb(hipStream_t s, const int32_t *ilist, int ni, int64_t maxnl, const InstDev *d) {
-  if (ni <= 0 || maxnl <= 0) return;
-  const int64_t nb = (maxnl + BLOCK - 1) / BLOCK;
+void op_refresh_pb(hipStream_t s, const int32_t *ilist, int ni, int64_t maxcount, const InstDev *d) {
+  if (ni <= 0 || maxcount <= 0) return;
+  const int64_t nb = (maxcount + BLOCK - 1) / BLOCK;
   const int gx = nb < 4096 ? (int)nb : 4096;
-  hipLaunchKernelGGL(k_low_pb, dim3(gx, ni), dim3(BLOCK), 0, s, ilist, d);
+  hipLaunchKernelGGL(k_refresh_pb, dim3(gx, ni), dim3(BLOCK), 0, s, ilist, d);
 }
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra) {
   if (ni <= 0) return;

@@ -305,11 +305,24 @@ void build_tiles(HostProblem &hp) {
   while (r0 < n) {
     int64_t ent = 0;
     int32_t r1 = r0;
+    bool capped = false;
     while (r1 < n && (r1 - r0) < row_target) {
       const int64_t e = (hp.rowptr_u[r1 + 1] - hp.rowptr_u[r1]) + (hp.rowptr_l[r1 + 1] - hp.rowptr_l[r1]);
-      if (r1 > r0 && ent + e > kEntCap) break;
+      if (r1 > r0 && ent + e > kEntCap) {
+        capped = true;
+        break;
+      }
       ent += e;
       ++r1;
+    }
+    // A tile closed by the entry cap has long rows, which the SpMM walks with
+    // a power-of-two number of lanes per row: 4..128 rows are cut to a power
+    // of two so that rows x lanes fill the workgroup (17 rows would leave
+    // 120 of 256 lanes idle, 16 rows use all of them).
+    if (capped && r1 - r0 >= 4 && r1 - r0 <= 128) {
+      int32_t p2 = 1;
+      while (p2 * 2 <= r1 - r0) p2 *= 2;
+      r1 = r0 + p2;
     }
     const double rows = (double)(r1 - r0);
     const double up = (double)(hp.rowptr_u[r1] - hp.rowptr_u[r0]) / rows;
