@@ -1376,10 +1376,21 @@ __device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nro
 #pragma unroll
     for (int u = 0; u < RQ; ++u) s[u] = 0.0;
     const double *src = I.part + (size_t)qb * I.prows + row0;
-    for (int t = tid; t < nrows; t += blockDim.x) {
+    // the loads of row t + blockDim.x are issued before row t is added, so
+    // each thread's rows cost one load latency each only when overlapped
+    double cur[RQ];
+    int t = tid;
 #pragma unroll
-      for (int u = 0; u < RQ; ++u)
-        if (u < nq) s[u] += src[(size_t)u * I.prows + t];
+    for (int u = 0; u < RQ; ++u) cur[u] = (u < nq && t < nrows) ? src[(size_t)u * I.prows + t] : 0.0;
+    for (; t < nrows; t += blockDim.x) {
+      const int tn = t + blockDim.x;
+      double nxt[RQ];
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) nxt[u] = (u < nq && tn < nrows) ? src[(size_t)u * I.prows + tn] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) s[u] += cur[u];
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
     for (int u = 0; u < RQ; ++u) {
