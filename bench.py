@@ -52,7 +52,7 @@ def workload(name):
 
 PROFILE_TAG = {"mc": "mc_1e5x1e5_r3", "torus": "torus_1000x1000_pm1", "er800": "maxcut_er800",
                "theta": "theta_er50000", "served": "served_maxcut"}
-CLASS_KERNEL = {"sddmm": "k_sddmm<", "spmm": "k_spmm<", "lanczos_spmv": "k_lz_spmv"}
+CLASS_KERNEL = {"sddmm": "k_sddmm<", "spmm": "k_spmm<", "lanczos_spmv": "k_lz_spmv", "sddmm_spmm": "k_trial_fused<"}
 
 
 def counted_traffic(workload_name, cls):

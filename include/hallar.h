@@ -110,6 +110,11 @@ typedef struct {
                                        pair is constrained with one shared coefficient and no sparse
                                        objective entry, it recomputes them from the factor rows and
                                        (p_l, b_l) kept in lower order.  Both give identical bits. */
+  int32_t unfused_trial;            /* 1: a FISTA trial point runs the SDDMM and the gradient SpMM as two
+                                       kernels; 0 (default): one kernel where the instance recomputes its
+                                       lower half, has no low-rank objective term and narrow rows
+                                       (r <= 8 in FP32-mixed, r <= 4 in FP64).  Both give identical bits. */
+  int32_t pad_;
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);

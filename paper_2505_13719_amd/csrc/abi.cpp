@@ -44,6 +44,7 @@ bool check_opts(const hallar_options &o, std::string &msg) {
   if (o.rank_cap < 0 || o.rank_cap > hl::R_MAX) { msg = "opts.rank_cap must be in [0, 64]"; return false; }
   if (o.eig_kmax < 0 || o.eig_kmax > hl::KMAX) { msg = "opts.eig_kmax must be in [0, 64]"; return false; }
   if (o.lower_gather != 0 && o.lower_gather != 1) { msg = "opts.lower_gather must be 0 or 1"; return false; }
+  if (o.unfused_trial != 0 && o.unfused_trial != 1) { msg = "opts.unfused_trial must be 0 or 1"; return false; }
   if (o.fista_max_iter < 1 || o.aipp_max_iter < 1 || o.hlr_max_iter < 1 || o.outer_max_iter < 1 || o.eig_max_iter < 1) {
     msg = "iteration caps must be >= 1";
     return false;

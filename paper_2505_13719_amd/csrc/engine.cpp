@@ -536,7 +536,7 @@ static void prof_collect(Pool &P) {
 
 // algorithmic bytes of one launch over the instances of a group
 struct GroupBytes {
-  double sddmm = 0, spmm_core = 0, urow = 0, lz_spmv = 0, vec_n8 = 0;
+  double sddmm = 0, spmm_core = 0, fused = 0, urow = 0, lz_spmv = 0, vec_n8 = 0;
 };
 
 static void launch_group(Pool &P, const Group &g, hipStream_t st);
@@ -548,11 +548,19 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
     const HostProblem &h = P.slots[s]->hp;
     const double n = h.n, Pp = (double)h.npairs, nl = (double)h.nlower, m = h.m;
     b.urow += n * R * sz;
-    b.sddmm += n * R * sz + (n + 1) * 4 + Pp * (4 + (h.direct ? 4 + (h.pa_uniform ? 0 : sz) : 0) +
-                                                 (h.has_c && !h.c_diag_only ? sz : 0)) +
-               (h.c_diag_only ? 8 * n : 0) + 16 * m;
+    // factor rows once, row pointers, per pair: column, then (direct) constraint
+    // id, {p_l, b_l} and the coefficient unless shared, the objective entry
+    // unless diagonal-only; general mode reads b and p per constraint
+    const double sd = n * R * sz + (n + 1) * 4 +
+                      Pp * (4 + (h.direct ? 4 + 16 + (h.pa_uniform ? 0 : sz) : 0) + (h.has_c && !h.c_diag_only ? sz : 0)) +
+                      (h.c_diag_only ? 8 * n : 0) + (h.direct ? 0 : 16 * m);
+    b.sddmm += sd;
     // lower half: column and pair id, or column and (p_l, b_l) when recomputed
     b.spmm_core += n * R * sz + 2 * (n + 1) * 4 + Pp * (4 + sz) + nl * (h.low_recompute ? 20 : 8);
+    // fused trial: the SDDMM's reads (no pair values written), the lower
+    // row pointers, columns and {p_l, b_l}; the SpMM epilogue is added by
+    // the caller
+    b.fused += sd + (n + 1) * 4 + nl * 20;
     b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 8 + 2 * (n + 1) * 4;
     b.vec_n8 += n * 8;
   }
@@ -577,8 +585,13 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   double msum = 0, psum = 0;
   bool any_lr = false;
   int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
+  // the trial's SDDMM and gradient SpMM run as one kernel when every instance
+  // recomputes its lower half, has no low-rank objective term (its product
+  // is reduced between the two) and the rows are narrow
+  bool fuse = !P.opts.unfused_trial && gni == 0 && trial_fusable(prec, R);
   for (int s : g.slots) {
     const HostProblem &h = P.slots[s]->hp;
+    fuse = fuse && h.direct && h.low_recompute && h.r0 == 0;
     msum += h.m;
     psum += (double)h.npairs;
     any_lr = any_lr || h.r0 > 0;
@@ -608,12 +621,20 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         op_combo(prec, R, st, T, nt, D);
       }
       red(RDH_COMBO, 0);
-      sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
-      {
-        ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
-        op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
+      if (fuse) {
+        {
+          ProfScope ps(P, KC_FUSED, B.fused + 3 * B.urow, st);
+          op_trial_fused(prec, R, st, T, nt, D, RXT);
+        }
+        red(RDH_TRIAL_FUSED, 0);
+      } else {
+        sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
+        {
+          ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
+          op_spmm(prec, R, st, T, nt, D, RXT, 0, 0, 0, SPM_TRIAL);
+        }
+        red(RDH_TRIAL_PROJ, 0);
       }
-      red(RDH_TRIAL_PROJ, 0);
       {
         ProfScope ps(P, KC_VEC, 5 * B.urow, st);
         op_proj(prec, R, st, T, nt, D);

@@ -23,6 +23,8 @@ constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR
 constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos SpMV
 constexpr int LZ_WP_SLOT = PSTRIDE - 2;  // partial ||w'||^2 after the first Gram-Schmidt pass
 constexpr int LZ_KV_SLOT = PSTRIDE - 4;  // partial K0^T w' (LR_MAX slots)
+constexpr int FUSE_SLOT = PSTRIDE - 8;   // the fused trial kernel's SpMM partials (2 slots)
+static_assert(FUSE_SLOT >= 4 + LR_MAX * R_MAX, "fused-trial slots overlap the low-rank slots");
 constexpr int NRES = 32;         // result scalars per instance
 constexpr int TILE_MAX_ROWS = 1024;     // rows of a tile (row pointers staged in LDS)
 constexpr int TILE_MAX_ENTRIES = 2048;  // entries of S u S^T staged per tile (longer tiles: single rows)

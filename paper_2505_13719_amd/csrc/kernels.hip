@@ -140,31 +140,19 @@ struct SddmmArgs {
 
 // Narrow rows (at most two 16-byte chunks): one thread per pair holds both
 // rows, all of a pair's loads are independent, no LDS round trip beyond the
-// tile's row pointers; two pairs per thread in flight.
+// tile's row pointers (s_rp); two pairs per thread in flight.
 template <typename T, int G>
-__device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
-                                             const SddmmArgs &a) {
+__device__ __forceinline__ void sddmm_narrow_pairs(const Tile &tl, const InstDev &I, const InstParams &P,
+                                                   const SddmmArgs &a, const T *__restrict__ X,
+                                                   const int32_t *s_rp, int nrows, T *mout, double (&acc)[4]) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  constexpr int NQ = 4;
   constexpr int UP = 2;
-  __shared__ int32_t s_rp[TILE_MAX_ROWS + 1];
-  const Tile tl = tiles[tile_index()];
-  const InstDev &I = insts[tl.inst];
-  const InstParams &P = *I.prm;
-  const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
   const T *__restrict__ cu = reinterpret_cast<const T *>(I.c_u);
   const T *__restrict__ pa = reinterpret_cast<const T *>(I.pa);
-  T *mout = a.msel == 0 ? reinterpret_cast<T *>(I.m_xt) : (a.msel == 1 ? reinterpret_cast<T *>(I.m_yp) : nullptr);
   const double beta = P.beta;
   const int direct = I.direct;
-  const int nrows = tl.row1 - tl.row0;
-  for (int r = threadIdx.x; r <= nrows; r += BLOCK) s_rp[r] = I.rowptr_u[tl.row0 + r];
-  __syncthreads();
   const int kbeg = s_rp[0], kend = s_rp[nrows];
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
   for (int kb = kbeg + threadIdx.x; kb < kend; kb += BLOCK * UP) {
     int kk[UP], ii[UP], jj[UP], l[UP];
     double cv[UP], av[UP], bl[UP], pl[UP];
@@ -229,7 +217,23 @@ __device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, con
       }
     }
   }
-  block_partials<NQ>(acc, I, tl.lt);
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void sddmm_narrow(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                             const SddmmArgs &a) {
+  __shared__ int32_t s_rp[TILE_MAX_ROWS + 1];
+  const Tile tl = tiles[tile_index()];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, a.xrole);
+  T *mout = a.msel == 0 ? reinterpret_cast<T *>(I.m_xt) : (a.msel == 1 ? reinterpret_cast<T *>(I.m_yp) : nullptr);
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) s_rp[r] = I.rowptr_u[tl.row0 + r];
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  sddmm_narrow_pairs<T, G>(tl, I, P, a, X, s_rp, nrows, mout, acc);
+  block_partials<4>(acc, I, tl.lt);
 }
 
 template <typename T, int G>
@@ -622,13 +626,94 @@ __device__ __forceinline__ void spmm_epi_apply(const InstDev &I, const InstParam
   }
 }
 
+// Rows of a staged tile (columns and, unless recomputed, pair values of
+// S u S^T in LDS): a team of G * S lanes per row walks the upper entries,
+// then the lower ones, and applies the row epilogue.
+template <typename T, int G, int MODE, int NQ>
+__device__ __forceinline__ void spmm_staged_rows(const Tile &tl, const InstDev &I, const InstParams &P,
+                                                 const SpmmArgs &a, const T *__restrict__ X, const int32_t *s_ru,
+                                                 const int32_t *s_rl, const int32_t *s_col, const T *s_m, int nrows,
+                                                 int ku0, int nu, int kl0, bool rec, double (&acc)[NQ]) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int UN = 4;  // gathers in flight per lane (measured: 4 beats 8 on the torus and MC)
+  const double beta = P.beta, a_low = I.pa_const;
+  const double2 *__restrict__ low_pb = reinterpret_cast<const double2 *>(I.low_pb);
+  // a team of G * S lanes per row: S pair streams (power of two) when the
+  // tile has fewer rows than the block has G-lane groups (long rows)
+  int S = 1;
+  while (S * 2 * G <= 64 && nrows * S * 2 * G <= BLOCK) S *= 2;
+  const int TS = G * S;
+  const int team = threadIdx.x / TS, lt = threadIdx.x - team * TS;
+  const int strm = lt / G, ch = lt - strm * G;
+  const int nteams = BLOCK / TS;
+  for (int rb = 0; rb < nrows; rb += nteams) {
+    const int r = rb + team;
+    if (r >= nrows) continue;
+    const int i = tl.row0 + r;
+    EpiIn<T> in;
+    if (strm == 0) in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
+    const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
+    const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
+    // own row (chunk ch) and the row's (p_l, b_l) for recomputed values
+    Chunk<T> xo;
+    if (rec && cnt > cu) xo = ldc(X + (size_t)i * R + ch * NC);
+    const double2 *__restrict__ pbr = rec ? low_pb + (s_rl[r] - cu) : nullptr;
+    // FP64 accumulation (also for FP32 data): near a stationary point the
+    // row sum cancels, and the FISTA / AIPP tests need the gradient to
+    // relative accuracy, not to the size of its terms
+    double w[NC];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) w[e] = 0.0;
+    for (int q = strm * UN; q < cnt; q += S * UN) {
+      Chunk<T> x[UN];
+      T mv[UN];
+      double2 pb[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int idx = q + u;
+        if (idx < cnt) {
+          const int pos = idx < cu ? a0 + idx : b0 + idx;
+          if (rec && idx >= cu) pb[u] = pbr[idx];
+          else mv[u] = s_m[pos];
+          x[u] = ldc(X + (size_t)s_col[pos] * R + ch * NC);
+        } else {
+          mv[u] = T(0);
+#pragma unroll
+          for (int e = 0; e < NC; ++e) x[u].v[e] = T(0);
+        }
+      }
+      if (rec) {
+        // lanes of a G-group share idx, so the butterfly stays inside
+        // lanes that take this branch together
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const int idx = q + u;
+          if (idx >= cu && idx < cnt) {
+            const double B = group_sum<G>(chunk_dot(x[u], xo));
+            mv[u] = (T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int e = 0; e < NC; ++e) w[e] += (double)mv[u] * (double)x[u].v[e];
+    }
+    for (int o = TS / 2; o >= G; o >>= 1) {
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
+    }
+    if (strm == 0) spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
+  }
+}
+
 template <typename T, int G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                 SpmmArgs a) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
   constexpr int NQ = MODE == SP_AIPP ? 4 : (MODE == SP_TRIAL ? 2 : 1);
-  constexpr int UN = 4;  // gathers in flight per lane (measured: 4 beats 8 on the torus and MC)
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   __shared__ int32_t s_col[TILE_MAX_ENTRIES];
   __shared__ T s_m[TILE_MAX_ENTRIES];
@@ -661,75 +746,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
     // stage the tile's columns and pair values of S u S^T (upper part, then
     // the lower transpose through its pair ids) with coalesced loads
     stage_entries<T>(I, m, ku0, nu, kl0, nl, !rec, s_col, s_m);
-    const double beta = P.beta, a_low = I.pa_const;
-    const double2 *__restrict__ low_pb = reinterpret_cast<const double2 *>(I.low_pb);
-    // a team of G * S lanes per row: S pair streams (power of two) when the
-    // tile has fewer rows than the block has G-lane groups (long rows)
-    int S = 1;
-    while (S * 2 * G <= 64 && nrows * S * 2 * G <= BLOCK) S *= 2;
-    const int TS = G * S;
-    const int team = threadIdx.x / TS, lt = threadIdx.x - team * TS;
-    const int strm = lt / G, ch = lt - strm * G;
-    const int nteams = BLOCK / TS;
-    for (int rb = 0; rb < nrows; rb += nteams) {
-      const int r = rb + team;
-      if (r >= nrows) continue;
-      const int i = tl.row0 + r;
-      EpiIn<T> in;
-      if (strm == 0) in = spmm_epi_load<T, G, MODE>(I, P, X, (size_t)i * R + ch * NC);
-      const int a0 = s_ru[r] - ku0, cu = s_ru[r + 1] - s_ru[r];
-      const int b0 = nu + s_rl[r] - kl0 - cu, cnt = cu + s_rl[r + 1] - s_rl[r];
-      // own row (chunk ch) and the row's (p_l, b_l) for recomputed values
-      Chunk<T> xo;
-      if (rec && cnt > cu) xo = ldc(X + (size_t)i * R + ch * NC);
-      const double2 *__restrict__ pbr = rec ? low_pb + (s_rl[r] - cu) : nullptr;
-      // FP64 accumulation (also for FP32 data): near a stationary point the
-      // row sum cancels, and the FISTA / AIPP tests need the gradient to
-      // relative accuracy, not to the size of its terms
-      double w[NC];
-#pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] = 0.0;
-      for (int q = strm * UN; q < cnt; q += S * UN) {
-        Chunk<T> x[UN];
-        T mv[UN];
-        double2 pb[UN];
-#pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const int idx = q + u;
-          if (idx < cnt) {
-            const int pos = idx < cu ? a0 + idx : b0 + idx;
-            if (rec && idx >= cu) pb[u] = pbr[idx];
-            else mv[u] = s_m[pos];
-            x[u] = ldc(X + (size_t)s_col[pos] * R + ch * NC);
-          } else {
-            mv[u] = T(0);
-#pragma unroll
-            for (int e = 0; e < NC; ++e) x[u].v[e] = T(0);
-          }
-        }
-        if (rec) {
-          // lanes of a G-group share idx, so the butterfly stays inside
-          // lanes that take this branch together
-#pragma unroll
-          for (int u = 0; u < UN; ++u) {
-            const int idx = q + u;
-            if (idx >= cu && idx < cnt) {
-              const double B = group_sum<G>(chunk_dot(x[u], xo));
-              mv[u] = (T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UN; ++u)
-#pragma unroll
-          for (int e = 0; e < NC; ++e) w[e] += (double)mv[u] * (double)x[u].v[e];
-      }
-      for (int o = TS / 2; o >= G; o >>= 1) {
-#pragma unroll
-        for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
-      }
-      if (strm == 0) spmm_epi_apply<T, G, MODE, NQ>(I, P, a, i, ch, w, in, acc);
-    }
+    spmm_staged_rows<T, G, MODE, NQ>(tl, I, P, a, X, s_ru, s_rl, s_col, s_m, nrows, ku0, nu, kl0, rec, acc);
   } else {
     // a tile too long to stage (one row of very high degree): teams of
     // G << plog lanes, 2^plog pair streams per row, read from HBM
@@ -769,6 +786,129 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
     }
   }
   if (MODE != SP_PLAIN) block_partials<NQ>(acc, I, tl.lt);
+}
+
+// FISTA trial point (Section 3.2, ADAP-FISTA): the SDDMM at XT and the
+// gradient SpMM at XT in one pass, for direct instances whose lower half is
+// recomputed, with no low-rank objective term and narrow rows (G <= 2).  The
+// row walk of the SpMM recomputes every entry's value from the two factor
+// rows -- the neighbour row is gathered once for the product and for the
+// accumulation -- and {p_l, b_l} in pair order (upper entries) or lower order
+// (lower entries), and the upper entries, which are the pairs of the tile's
+// own rows, also feed the SDDMM's partial sums (slots 0..3).  Per pair that
+// is one gather of a factor row instead of three (SDDMM, SpMM upper and
+// lower), and no pair values written or read.  The pair values and the
+// SpMM's sums are bit-identical to the separate kernels'; the SDDMM's partial
+// sums are formed in walk order instead of pair order.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ tiles,
+                                                       const InstDev *__restrict__ insts, int32_t xrole) {
+  static_assert(G <= 2, "the fused trial kernel takes narrow rows");
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  constexpr int UN = 4;
+  __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
+  const Tile tl = tiles[tile_index()];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *__restrict__ X = role_ptr<T>(I, P, xrole);
+  const int nrows = tl.row1 - tl.row0;
+  for (int r = threadIdx.x; r <= nrows; r += BLOCK) {
+    s_ru[r] = I.rowptr_u[tl.row0 + r];
+    s_rl[r] = I.rowptr_l[tl.row0 + r];
+  }
+  __syncthreads();
+  const double beta = P.beta, a_low = I.pa_const;
+  const T *__restrict__ cuv = reinterpret_cast<const T *>(I.c_u);
+  const T *__restrict__ pav = reinterpret_cast<const T *>(I.pa);
+  const double2 *__restrict__ upb = reinterpret_cast<const double2 *>(I.upb);
+  const double2 *__restrict__ low_pb = reinterpret_cast<const double2 *>(I.low_pb);
+  const SpmmArgs sa{xrole, 0, 0, 0};
+  // teams as in the staged SpMM: G * S lanes per row
+  int S = 1;
+  while (S * 2 * G <= 64 && nrows * S * 2 * G <= BLOCK) S *= 2;
+  const int TS = G * S;
+  const int team = threadIdx.x / TS, lt = threadIdx.x - team * TS;
+  const int strm = lt / G, ch = lt - strm * G;
+  const int nteams = BLOCK / TS;
+  double acc4[4] = {0.0, 0.0, 0.0, 0.0};  // T0, p^T r, ||r||^2, sum y' T
+  double acc2[2] = {0.0, 0.0};            // ||Z||^2, ||GR||^2
+  for (int rb = 0; rb < nrows; rb += nteams) {
+    const int r = rb + team;
+    if (r >= nrows) continue;
+    const int i = tl.row0 + r;
+    EpiIn<T> in;
+    if (strm == 0) in = spmm_epi_load<T, G, SP_TRIAL>(I, P, X, (size_t)i * R + ch * NC);
+    const int ku = s_ru[r], cu = s_ru[r + 1] - ku;
+    const int kl = s_rl[r], cnt = cu + s_rl[r + 1] - kl;
+    const Chunk<T> xo = ldc(X + (size_t)i * R + ch * NC);
+    double w[NC];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) w[e] = 0.0;
+    for (int q = strm * UN; q < cnt; q += S * UN) {
+      Chunk<T> x[UN];
+      double2 pb[UN];
+      int col[UN], lk[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int idx = q + u;
+        lk[u] = 0;
+        if (idx < cnt) {
+          if (idx < cu) {
+            const int k = ku + idx;
+            col[u] = I.col_u[k];
+            lk[u] = I.pcon[k];
+            pb[u] = upb[k];
+          } else {
+            const int e = kl + idx - cu;
+            col[u] = I.col_l[e];
+            pb[u] = low_pb[e];
+          }
+          x[u] = ldc(X + (size_t)col[u] * R + ch * NC);
+        }
+      }
+      // lanes of a G-group share idx: the butterfly stays inside lanes that
+      // take the branch together, and one lane of the group adds the SDDMM
+      // sums
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int idx = q + u;
+        if (idx >= cnt) continue;
+        const double B = group_sum<G>(chunk_dot(x[u], xo));
+        double mv;
+        if (idx < cu) {
+          const int k = ku + idx;
+          const bool dg = col[u] == i;
+          const double w2 = dg ? 1.0 : 2.0;
+          const double cv = I.c_diag_only ? (dg ? I.c_diag[i] : 0.0) : (cuv ? (double)cuv[k] : 0.0);
+          if (ch == 0) acc4[0] += w2 * cv * B;
+          mv = cv;
+          if (lk[u] > 0) {
+            const double av = I.pa_uniform ? I.pa_const : (double)pav[k];
+            const PairAL qv = pair_al(cv, av, pb[u].y, pb[u].x, beta, B, w2);
+            if (ch == 0) {
+              acc4[1] += pb[u].x * qv.r;
+              acc4[2] += qv.r * qv.r;
+              acc4[3] += qv.y * qv.t;
+            }
+            mv = qv.m;
+          }
+        } else {
+          mv = pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
+        }
+        const double mt = (double)(T)mv;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) w[e] += mt * (double)x[u].v[e];
+      }
+    }
+    for (int o = TS / 2; o >= G; o >>= 1) {
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
+    }
+    if (strm == 0) spmm_epi_apply<T, G, SP_TRIAL, 2>(I, P, sa, i, ch, w, in, acc2);
+  }
+  block_partials<4>(acc4, I, tl.lt);
+  block_partials<2, FUSE_SLOT>(acc2, I, tl.lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1351,8 +1491,9 @@ enum RedOp : int {
   RD_NORM,         // ||.||^2 of a pack / copy
   RD_GEN_EXTRA,    // general mode: add constraint-major p^T r, ||r||^2 rows
   RD_GRAM,         // sum gram partials
-  RD_LZ_CHECKH2    // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2),
+  RD_LZ_CHECKH2,   // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2),
                    // else h2 -> hcoef, H column += h2
+  RD_TRIAL_FUSED   // RD_SDDMM_XT and RD_TRIAL_PROJ (from FUSE_SLOT) after the fused trial kernel
 };
 
 struct RedArgs {
@@ -1457,6 +1598,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       break;
     }
     case RD_SDDMM_XT:
+    case RD_TRIAL_FUSED:
     case RD_SDDMM_YP:
     case RD_EVAL: {
       const int nlr = I.r0 * a.R;
@@ -1471,7 +1613,8 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       if (tid == 0) {
         const double t0 = S[0] + tr, pr = S[1] + E[0], rr = S[2] + E[1], yt = S[3] + E[2];
         const double g = t0 + pr + 0.5 * P.beta * rr;
-        const int slot = a.op == RD_SDDMM_XT ? S_G_XT : (a.op == RD_SDDMM_YP ? S_G_YP : S_G_EVAL);
+        const int slot =
+            a.op == RD_SDDMM_XT || a.op == RD_TRIAL_FUSED ? S_G_XT : (a.op == RD_SDDMM_YP ? S_G_YP : S_G_EVAL);
         res[slot] = g;
         if (a.op == RD_EVAL) {
           res[S_T0] = t0;
@@ -1480,6 +1623,15 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
           res[S_YT] = yt;
         }
         if (!(g == g) || g - g != 0.0) res[S_NAN] = 1.0;
+      }
+      if (a.op == RD_TRIAL_FUSED) {
+        __syncthreads();
+        reduce_slots(I, FUSE_SLOT, FUSE_SLOT + 2, 0, nt, S);
+        if (tid == 0) {
+          res[S_NZ] = S[0];
+          res[S_PROJC] = S[0] > P.tau2 ? P.tau / sqrt(S[0]) : 1.0;
+          res[S_GR2T] = S[1];
+        }
       }
       break;
     }
@@ -1685,6 +1837,21 @@ void op_spmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDe
   SpmmArgs a{xrole, msel, zsel, outrole};
   if (is64(prec)) HL_DISPATCH_G(double, R, l_spmm, s, t, nt, d, a, mode);
   else HL_DISPATCH_G(float, R, l_spmm, s, t, nt, d, a, mode);
+}
+bool trial_fusable(int prec, int R) {
+  const int G = is64(prec) ? g_of<double>(R) : g_of<float>(R);
+  return G == 1 || G == 2;
+}
+void op_trial_fused(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole) {
+  if (nt <= 0) return;
+  const int G = is64(prec) ? g_of<double>(R) : g_of<float>(R);
+  if (is64(prec)) {
+    if (G == 1) hipLaunchKernelGGL((k_trial_fused<double, 1>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
+    else if (G == 2) hipLaunchKernelGGL((k_trial_fused<double, 2>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
+  } else {
+    if (G == 1) hipLaunchKernelGGL((k_trial_fused<float, 1>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
+    else if (G == 2) hipLaunchKernelGGL((k_trial_fused<float, 2>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
+  }
 }
 void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d) {
   if (nt <= 0) return;

@@ -10,7 +10,7 @@ enum SpmmModeH : int { SPM_PLAIN = 0, SPM_TRIAL = 1, SPM_AIPP = 2 };
 enum RedOpH : int {
   RDH_COMBO = 0, RDH_SDDMM_XT, RDH_TRIAL_PROJ, RDH_PROJ_DOTS, RDH_SDDMM_YP, RDH_AIPP, RDH_EVAL, RDH_LRONLY,
   RDH_LZ_START, RDH_LZ_H1, RDH_LZ_H2, RDH_LZ_FINAL, RDH_FW_DEN, RDH_SETP, RDH_NORM, RDH_GEN_EXTRA, RDH_GRAM,
-  RDH_LZ_CHECKH2
+  RDH_LZ_CHECKH2, RDH_TRIAL_FUSED
 };
 
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp);
@@ -18,6 +18,9 @@ void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const Ins
 void op_spmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int zsel,
              int outrole, int mode);
 void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
+// SDDMM + gradient SpMM at the trial point in one kernel (narrow rows only)
+bool trial_fusable(int prec, int R);
+void op_trial_fused(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);
 void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_copy_scale(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst);
 void op_gram(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src);

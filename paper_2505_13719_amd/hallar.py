@@ -42,7 +42,7 @@ class hallar_options(C.Structure):
                 ("eig_frac", C.c_double), ("eig_kmax", C.c_int32), ("eig_max_iter", C.c_int32),
                 ("rank_cap", C.c_int32), ("drop_tol", C.c_double), ("time_limit", C.c_double),
                 ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32), ("autotune", C.c_int32),
-                ("lower_gather", C.c_int32)]
+                ("lower_gather", C.c_int32), ("unfused_trial", C.c_int32), ("pad_", C.c_int32)]
 
 
 class hallar_result(C.Structure):
@@ -363,7 +363,7 @@ def hallar_pool_usage(pool):
     return u.value, b.value
 
 
-KERNEL_CLASSES = ["sddmm", "spmm", "lanczos_spmv", "lanczos_reorth", "vector", "reduce", "other"]
+KERNEL_CLASSES = ["sddmm", "spmm", "lanczos_spmv", "lanczos_reorth", "vector", "reduce", "other", "sddmm_spmm"]
 
 
 def _profile(fn, obj, reset):

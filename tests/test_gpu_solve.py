@@ -178,38 +178,55 @@ def test_autotuned_schedule_solves_alike():
 
 
 LOWER_CASES = [
-    ("mc_300x400", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP32_MIXED, 1),
-    ("mc_300x400_fp64", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP64, 1),
-    ("theta_er150", lambda: _make("theta_er150", None), H.FP64, 1),
-    # a 12-column start: 16-column FP32 rows, four lanes per row (butterfly dots)
-    ("mc_wide_fp32", lambda: si.mc_planted(200, 300, 6, 15000, seed=9), H.FP32_MIXED, 12),
+    ("mc_300x400", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP32_MIXED, 1, True),
+    ("mc_300x400_fp64", lambda: si.mc_planted(300, 400, 2, 20000, seed=8), H.FP64, 1, True),
+    # low-rank objective term: recomputed lower half, never fused
+    ("theta_er150", lambda: _make("theta_er150", None), H.FP64, 1, False),
+    # a 12-column start: 16-column FP32 rows, four lanes per row (butterfly
+    # dots), fused only once the rank falls to 8 or less
+    ("mc_wide_fp32", lambda: si.mc_planted(200, 300, 6, 15000, seed=9), H.FP32_MIXED, 12, None),
 ]
 
 
-@pytest.mark.parametrize("name,maker,prec,r0", LOWER_CASES, ids=[c[0] for c in LOWER_CASES])
-def test_lower_recompute_bitwise(name, maker, prec, r0):
+@pytest.mark.parametrize("name,maker,prec,r0,fused", LOWER_CASES, ids=[c[0] for c in LOWER_CASES])
+def test_lower_recompute_and_fusion_bitwise(name, maker, prec, r0, fused):
     """The gradient SpMM's lower half recomputed from the factor rows and
     (p_l, b_l) in lower order (opts.lower_gather = 0) takes the SDDMM's
-    arithmetic, so the whole solve is bit-identical to the one that gathers
-    the SDDMM's pair values (lower_gather = 1).  The SpMM's algorithmic bytes
-    tell the two paths apart (column + (p_l, b_l) vs column + pair id)."""
+    arithmetic, so that solve is bit-identical to the gathering one.  The
+    fused trial kernel (opts.unfused_trial = 0) forms the same pair values
+    and SpMM sums but adds the SDDMM's partial sums in walk order, so its
+    solve agrees to the solve tolerance.  The profile tells the paths apart:
+    the SpMM's algorithmic bytes (column + (p_l, b_l) vs column + pair id)
+    and the fused kernel's launches."""
     d = dev()
     prob = maker()
     out = {}
-    for lg in (1, 0):
-        h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, lower_gather=lg))
+    for cfg in ((1, 1), (0, 1), (0, 0)):
+        lg, uf = cfg
+        h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, lower_gather=lg, unfused_trial=uf))
         try:
             U_0 = np.random.default_rng(7).standard_normal((prob.n, r0))
             res = H.hallar_solve(h, torch.tensor(U_0, device=d))
             U = torch.empty((prob.n, max(res["rank"], 1)), dtype=torch.float64, device=d)
             p = torch.empty(max(prob.m, 1), dtype=torch.float64, device=d)
             H.hallar_get_solution(h, U, p)
-            out[lg] = (res, U.cpu().numpy(), p.cpu().numpy(), H.hallar_profile(h))
+            out[cfg] = (res, U.cpu().numpy(), p.cpu().numpy(), H.hallar_profile(h))
         finally:
             H.hallar_destroy(h)
-    (r1, U1, p1, f1), (r0, U0, p0, f0) = out[1], out[0]
-    assert r0["status"] == "ok", r0
+    r1, U1, p1, f1 = out[(1, 1)]
+    assert r1["status"] == "ok", r1
+    r0_, U0_, p0_, _ = out[(0, 1)]
     for k in ("pval", "dval", "gap", "pinf", "rank", "outer_iters", "n_fista_trials", "n_spmm", "n_hlr_iters"):
-        assert r0[k] == r1[k], (k, r0[k], r1[k])
-    assert np.array_equal(U0, U1) and np.array_equal(p0, p1)
-    assert f0["spmm"]["bytes"] != f1["spmm"]["bytes"]
+        assert r0_[k] == r1[k], (k, r0_[k], r1[k])
+    assert np.array_equal(U0_, U1) and np.array_equal(p0_, p1)
+    rf = out[(0, 0)][0]
+    assert rf["status"] == "ok", rf
+    assert max(rf["pinf"], rf["gap"], rf["dinf"]) <= 1e-5
+    assert abs(rf["pval"] - r1["pval"]) <= 1e-5 * (1 + abs(r1["pval"])), (rf["pval"], r1["pval"])
+    assert out[(0, 1)][3]["spmm"]["bytes"] != f1["spmm"]["bytes"]
+    assert out[(0, 1)][3]["sddmm_spmm"]["launches"] == 0 and f1["sddmm_spmm"]["launches"] == 0
+    nf = out[(0, 0)][3]["sddmm_spmm"]["launches"]
+    if fused is True:
+        assert nf > 0
+    elif fused is False:
+        assert nf == 0
