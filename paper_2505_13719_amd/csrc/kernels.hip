@@ -640,7 +640,9 @@ __device__ __forceinline__ void spmm_staged_rows(const Tile &tl, const InstDev &
   const double beta = P.beta, a_low = I.pa_const;
   const double2 *__restrict__ low_pb = reinterpret_cast<const double2 *>(I.low_pb);
   // a team of G * S lanes per row: S pair streams (power of two) when the
-  // tile has fewer rows than the block has G-lane groups (long rows)
+  // tile has fewer rows than the block has G-lane groups (long rows); stream
+  // s takes the row's entries s, s + S, s + 2S, ..., UN at a time, so the
+  // streams of a team read consecutive entries together
   int S = 1;
   while (S * 2 * G <= 64 && nrows * S * 2 * G <= BLOCK) S *= 2;
   const int TS = G * S;
@@ -665,13 +667,13 @@ __device__ __forceinline__ void spmm_staged_rows(const Tile &tl, const InstDev &
     double w[NC];
 #pragma unroll
     for (int e = 0; e < NC; ++e) w[e] = 0.0;
-    for (int q = strm * UN; q < cnt; q += S * UN) {
+    for (int q = strm; q < cnt; q += S * UN) {
       Chunk<T> x[UN];
       T mv[UN];
       double2 pb[UN];
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int idx = q + u;
+        const int idx = q + u * S;
         if (idx < cnt) {
           const int pos = idx < cu ? a0 + idx : b0 + idx;
           if (rec && idx >= cu) pb[u] = pbr[idx];
@@ -688,7 +690,7 @@ __device__ __forceinline__ void spmm_staged_rows(const Tile &tl, const InstDev &
         // lanes that take this branch together
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
-          const int idx = q + u;
+          const int idx = q + u * S;
           if (idx >= cu && idx < cnt) {
             const double B = group_sum<G>(chunk_dot(x[u], xo));
             mv[u] = (T)pair_al(0.0, a_low, pb[u].y, pb[u].x, beta, B, 2.0).m;
@@ -845,13 +847,13 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
     double w[NC];
 #pragma unroll
     for (int e = 0; e < NC; ++e) w[e] = 0.0;
-    for (int q = strm * UN; q < cnt; q += S * UN) {
+    for (int q = strm; q < cnt; q += S * UN) {
       Chunk<T> x[UN];
       double2 pb[UN];
       int col[UN], lk[UN];
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int idx = q + u;
+        const int idx = q + u * S;
         lk[u] = 0;
         if (idx < cnt) {
           if (idx < cu) {
@@ -872,7 +874,7 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
       // sums
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int idx = q + u;
+        const int idx = q + u * S;
         if (idx >= cnt) continue;
         const double B = group_sum<G>(chunk_dot(x[u], xo));
         double mv;
