@@ -640,9 +640,12 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         op_proj(prec, R, st, T, nt, D);
       }
       red(RDH_PROJ_DOTS, 0);
-      sddmm(RZ, 1, 0, 0, RDH_SDDMM_YP, 1);
+      // the AL value at y+ only: the pair values there are needed by the
+      // gradient at the accepted trial, which forms them itself (OP_GRAD)
+      sddmm(RZ, -1, 0, 0, RDH_SDDMM_YP, 1);
       break;
     case OP_GRAD:
+      sddmm(RZ, 1, 0, 0, RDH_SDDMM_YP, 1);
       {
         ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
         op_spmm(prec, R, st, T, nt, D, RZ, 1, 1, 0, SPM_AIPP);
