@@ -408,6 +408,7 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     v->hp.nentries = src.hp.nentries;
     v->hp.direct = src.hp.direct;
     v->hp.low_recompute = src.hp.low_recompute;
+    v->hp.con_rule = src.hp.con_rule;
     v->hp.has_c = src.hp.has_c;
     v->hp.r0 = src.hp.r0;
     v->hp.b_l1 = src.hp.b_l1;

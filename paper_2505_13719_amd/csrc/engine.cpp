@@ -407,6 +407,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.c64 = h.has_c ? (const double *)at(L.c64) : nullptr;
   D.pa64 = (const double *)at(L.pa64);
   D.pa_uniform = h.pa_uniform ? 1 : 0;
+  D.con_rule = h.direct ? h.con_rule : 0;
   D.pa_const = h.pa_const;
   D.c_diag_only = h.c_diag_only ? 1 : 0;
   D.c_diag = h.c_diag_only ? (const double *)at(L.c_diag) : nullptr;
@@ -552,7 +553,8 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
     // id, {p_l, b_l} and the coefficient unless shared, the objective entry
     // unless diagonal-only; general mode reads b and p per constraint
     const double sd = n * R * sz + (n + 1) * 4 +
-                      Pp * (4 + (h.direct ? 4 + 16 + (h.pa_uniform ? 0 : sz) : 0) + (h.has_c && !h.c_diag_only ? sz : 0)) +
+                      Pp * (4 + (h.direct ? (h.con_rule ? 0 : 4) + 16 + (h.pa_uniform ? 0 : sz) : 0) +
+                            (h.has_c && !h.c_diag_only ? sz : 0)) +
                       (h.c_diag_only ? 8 * n : 0) + (h.direct ? 0 : 16 * m);
     b.sddmm += sd;
     // lower half: column and pair id, or column and (p_l, b_l) when recomputed
@@ -620,7 +622,9 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         ProfScope ps(P, KC_VEC, 4 * B.urow, st);
         op_combo(prec, R, st, T, nt, D);
       }
-      red(RDH_COMBO, 0);
+      // partial sums go to disjoint slots so that one reduce serves several
+      // kernels: the extrapolation's with the fused trial's, the
+      // projection's with the SDDMM at y+
       if (fuse) {
         {
           ProfScope ps(P, KC_FUSED, B.fused + 3 * B.urow, st);
@@ -628,6 +632,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         }
         red(RDH_TRIAL_FUSED, 0);
       } else {
+        red(RDH_COMBO, 0);
         sddmm(RXT, 0, 0, 0, RDH_SDDMM_XT, 0);
         {
           ProfScope ps(P, KC_SPMM, B.spmm_core + 3 * B.urow, st);
@@ -639,10 +644,9 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         ProfScope ps(P, KC_VEC, 5 * B.urow, st);
         op_proj(prec, R, st, T, nt, D);
       }
-      red(RDH_PROJ_DOTS, 0);
       // the AL value at y+ only: the pair values there are needed by the
       // gradient at the accepted trial, which forms them itself (OP_GRAD)
-      sddmm(RZ, -1, 0, 0, RDH_SDDMM_YP, 1);
+      sddmm(RZ, -1, 0, 0, RDH_YP_PROJ, 1);
       break;
     case OP_GRAD:
       sddmm(RZ, 1, 0, 0, RDH_SDDMM_YP, 1);

@@ -31,6 +31,11 @@ struct HostProblem {
   // has no sparse objective entry: the gradient SpMM recomputes the lower
   // half's values from (p_l, b_l) kept in lower order
   bool low_recompute = false;
+  // direct mode: 1 if exactly the off-diagonal pairs are constrained (matrix
+  // completion, theta), 2 if exactly the diagonal ones are (MaxCut), else 0;
+  // kernels that only need to know whether a pair is constrained skip its
+  // constraint id then
+  int32_t con_rule = 0;
   // general mode (a constraint with several pairs or a pair in several constraints)
   std::vector<int32_t> eptr, econ, cptr, cent, epair;
   std::vector<double> ea, ew;

@@ -24,7 +24,11 @@ constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos S
 constexpr int LZ_WP_SLOT = PSTRIDE - 2;  // partial ||w'||^2 after the first Gram-Schmidt pass
 constexpr int LZ_KV_SLOT = PSTRIDE - 4;  // partial K0^T w' (LR_MAX slots)
 constexpr int FUSE_SLOT = PSTRIDE - 8;   // the fused trial kernel's SpMM partials (2 slots)
-static_assert(FUSE_SLOT >= 4 + LR_MAX * R_MAX, "fused-trial slots overlap the low-rank slots");
+constexpr int COMBO_SLOT = PSTRIDE - 6;  // the extrapolation's ||XT - W0||^2 partial
+constexpr int PROJ_SLOT = PSTRIDE - 12;  // the projection's three dot partials
+static_assert(PROJ_SLOT >= 4 + LR_MAX * R_MAX && PROJ_SLOT + 3 <= FUSE_SLOT,
+              "trial slots overlap the low-rank slots or each other");
+static_assert(COMBO_SLOT == FUSE_SLOT + 2 && COMBO_SLOT < LZ_KV_SLOT, "one reduce reads FUSE_SLOT..COMBO_SLOT");
 constexpr int NRES = 32;         // result scalars per instance
 constexpr int TILE_MAX_ROWS = 1024;     // rows of a tile (row pointers staged in LDS)
 constexpr int TILE_MAX_ENTRIES = 2048;  // entries of S u S^T staged per tile (longer tiles: single rows)
@@ -114,6 +118,7 @@ struct InstDev {
   double *upb;
   const void *c_u, *pa;                     // operator type: C_ij per pair, (A_l)_ij of the pair's constraint
   int32_t pa_uniform, c_diag_only;          // the SDDMM reads pa_const / c_diag instead of pa / c_u
+  int32_t con_rule;                         // 1: constrained <=> off-diagonal, 2: <=> diagonal, 0: read pcon
   double pa_const;
   const double *c_diag;                     // length n when c_diag_only
   const double *c64, *pa64, *b;             // FP64 copies, b (length m)

@@ -176,7 +176,10 @@ __device__ __forceinline__ void sddmm_narrow_pairs(const Tile &tl, const InstDev
         if (I.c_diag_only) cv[u] = ii[u] == jj[u] ? I.c_diag[ii[u]] : 0.0;
         else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
-          l[u] = I.pcon[k];
+          // the constraint id where T_l / y'_l are stored or no rule tells
+          // which pairs are constrained; else a flag (1: constrained)
+          if (a.write_T || a.write_yp || I.con_rule == 0) l[u] = I.pcon[k];
+          else l[u] = (I.con_rule == 1) != (ii[u] == jj[u]) ? 1 : 0;
           const double2 v = reinterpret_cast<const double2 *>(I.upb)[k];
           if (l[u] > 0) {
             av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
@@ -298,7 +301,8 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
         if (I.c_diag_only) cv[u] = tl.row0 + lo == jc ? I.c_diag[jc] : 0.0;
         else cv[u] = cu ? (double)cu[k] : 0.0;
         if (direct) {
-          l[u] = I.pcon[k];
+          if (a.write_T || a.write_yp || I.con_rule == 0) l[u] = I.pcon[k];
+          else l[u] = (I.con_rule == 1) != (tl.row0 + lo == jc) ? 1 : 0;
           const double2 v = reinterpret_cast<const double2 *>(I.upb)[k];
           if (l[u] > 0) {
             av[u] = I.pa_uniform ? I.pa_const : (double)pa[k];
@@ -859,7 +863,7 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
           if (idx < cu) {
             const int k = ku + idx;
             col[u] = I.col_u[k];
-            lk[u] = I.pcon[k];
+            if (!I.con_rule) lk[u] = I.pcon[k];
             pb[u] = upb[k];
           } else {
             const int e = kl + idx - cu;
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
           const double cv = I.c_diag_only ? (dg ? I.c_diag[i] : 0.0) : (cuv ? (double)cuv[k] : 0.0);
           if (ch == 0) acc4[0] += w2 * cv * B;
           mv = cv;
-          if (lk[u] > 0) {
+          if (I.con_rule ? (I.con_rule == 1) != dg : lk[u] > 0) {
             const double av = I.pa_uniform ? I.pa_const : (double)pav[k];
             const PairAL qv = pair_al(cv, av, pb[u].y, pb[u].x, beta, B, w2);
             if (ch == 0) {
@@ -955,7 +959,7 @@ __global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles,
     }
     stc(XTp + off, o);
   }
-  block_partials<1>(acc, I, tl.lt);
+  block_partials<1, COMBO_SLOT>(acc, I, tl.lt);
 }
 
 // y+ = c Z (projection onto the Frobenius ball, c from the reduce kernel),
@@ -990,7 +994,7 @@ __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, 
     }
     stc(Zp + off, z);
   }
-  block_partials<3>(acc, I, tl.lt);
+  block_partials<3, PROJ_SLOT>(acc, I, tl.lt);
 }
 
 // Copy role src -> role dst (scaled), optional partial ||dst||^2.
@@ -1495,7 +1499,8 @@ enum RedOp : int {
   RD_GRAM,         // sum gram partials
   RD_LZ_CHECKH2,   // after the first Gram-Schmidt pass: skip the second if ||w'|| >= ||w|| / sqrt(2),
                    // else h2 -> hcoef, H column += h2
-  RD_TRIAL_FUSED   // RD_SDDMM_XT and RD_TRIAL_PROJ (from FUSE_SLOT) after the fused trial kernel
+  RD_TRIAL_FUSED,  // RD_SDDMM_XT, RD_TRIAL_PROJ (from FUSE_SLOT) and RD_COMBO after the fused trial kernel
+  RD_YP_PROJ       // RD_SDDMM_YP and RD_PROJ_DOTS
 };
 
 struct RedArgs {
@@ -1587,7 +1592,8 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     case RD_COMBO:
     case RD_NORM:
     case RD_TRIAL_PROJ: {
-      reduce_slots(I, 0, a.op == RD_TRIAL_PROJ ? 2 : 1, 0, nt, S);
+      const int q0 = a.op == RD_COMBO ? COMBO_SLOT : 0;
+      reduce_slots(I, q0, q0 + (a.op == RD_TRIAL_PROJ ? 2 : 1), 0, nt, S);
       if (tid == 0) {
         if (a.op == RD_COMBO) res[S_XTW0] = S[0];
         else if (a.op == RD_NORM) res[S_NZ] = S[0];
@@ -1602,6 +1608,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     case RD_SDDMM_XT:
     case RD_TRIAL_FUSED:
     case RD_SDDMM_YP:
+    case RD_YP_PROJ:
     case RD_EVAL: {
       const int nlr = I.r0 * a.R;
       reduce_slots(I, 0, 4 + nlr, 0, nt, S);
@@ -1609,14 +1616,15 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       if (ex > 0) reduce_slots(I, 0, 3, nt, ex, E);
       else if (tid < 4) E[tid] = 0.0;
       __syncthreads();
-      const int zsel = a.op == RD_SDDMM_YP ? 1 : a.zsel;
+      const int zsel = a.op == RD_SDDMM_YP || a.op == RD_YP_PROJ ? 1 : a.zsel;
       double tr = 0.0;
       if (I.r0 > 0) tr = lowrank_finish(I, a.R, zsel, S + 4);
       if (tid == 0) {
         const double t0 = S[0] + tr, pr = S[1] + E[0], rr = S[2] + E[1], yt = S[3] + E[2];
         const double g = t0 + pr + 0.5 * P.beta * rr;
-        const int slot =
-            a.op == RD_SDDMM_XT || a.op == RD_TRIAL_FUSED ? S_G_XT : (a.op == RD_SDDMM_YP ? S_G_YP : S_G_EVAL);
+        const int slot = a.op == RD_SDDMM_XT || a.op == RD_TRIAL_FUSED
+                             ? S_G_XT
+                             : (a.op == RD_SDDMM_YP || a.op == RD_YP_PROJ ? S_G_YP : S_G_EVAL);
         res[slot] = g;
         if (a.op == RD_EVAL) {
           res[S_T0] = t0;
@@ -1628,18 +1636,28 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       }
       if (a.op == RD_TRIAL_FUSED) {
         __syncthreads();
-        reduce_slots(I, FUSE_SLOT, FUSE_SLOT + 2, 0, nt, S);
+        reduce_slots(I, FUSE_SLOT, FUSE_SLOT + 3, 0, nt, S);  // FUSE_SLOT + 2 = COMBO_SLOT
         if (tid == 0) {
           res[S_NZ] = S[0];
           res[S_PROJC] = S[0] > P.tau2 ? P.tau / sqrt(S[0]) : 1.0;
           res[S_GR2T] = S[1];
+          res[S_XTW0] = S[2];
+        }
+      } else if (a.op == RD_YP_PROJ) {
+        __syncthreads();
+        reduce_slots(I, PROJ_SLOT, PROJ_SLOT + 3, 0, nt, S);
+        if (tid == 0) {
+          res[S_GR_D] = S[0];
+          res[S_D2] = S[1];
+          res[S_YPW0] = S[2];
         }
       }
       break;
     }
     case RD_PROJ_DOTS:
     case RD_AIPP: {
-      reduce_slots(I, 0, a.op == RD_AIPP ? 4 : 3, 0, nt, S);
+      const int q0 = a.op == RD_PROJ_DOTS ? PROJ_SLOT : 0;
+      reduce_slots(I, q0, q0 + (a.op == RD_AIPP ? 4 : 3), 0, nt, S);
       if (tid == 0) {
         if (a.op == RD_PROJ_DOTS) {
           res[S_GR_D] = S[0];

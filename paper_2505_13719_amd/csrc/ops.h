@@ -10,7 +10,7 @@ enum SpmmModeH : int { SPM_PLAIN = 0, SPM_TRIAL = 1, SPM_AIPP = 2 };
 enum RedOpH : int {
   RDH_COMBO = 0, RDH_SDDMM_XT, RDH_TRIAL_PROJ, RDH_PROJ_DOTS, RDH_SDDMM_YP, RDH_AIPP, RDH_EVAL, RDH_LRONLY,
   RDH_LZ_START, RDH_LZ_H1, RDH_LZ_H2, RDH_LZ_FINAL, RDH_FW_DEN, RDH_SETP, RDH_NORM, RDH_GEN_EXTRA, RDH_GRAM,
-  RDH_LZ_CHECKH2, RDH_TRIAL_FUSED
+  RDH_LZ_CHECKH2, RDH_TRIAL_FUSED, RDH_YP_PROJ
 };
 
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp);

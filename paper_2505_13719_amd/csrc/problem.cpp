@@ -128,6 +128,14 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
       }
     hp.pa_uniform = uni && !first;
     hp.pa_const = a0;
+    bool off = direct, on = direct;
+    for (int32_t i = 0; i < n && (off || on); ++i)
+      for (int32_t k = hp.rowptr_u[i]; k < hp.rowptr_u[i + 1]; ++k) {
+        const bool dg = hp.col_u[k] == i, con = hp.pcon[k] > 0;
+        if (con == dg) off = false;
+        if (con != dg) on = false;
+      }
+    hp.con_rule = off ? 1 : (on ? 2 : 0);
     bool diag = has_c;
     for (int32_t i = 0; i < n && diag; ++i)
       for (int32_t k = hp.rowptr_u[i]; k < hp.rowptr_u[i + 1]; ++k)
