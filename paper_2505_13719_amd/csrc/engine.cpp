@@ -316,6 +316,7 @@ static void put(char *base, size_t off, const std::vector<T> &v, hipStream_t st)
 }
 
 hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
+  P.tile_epoch++;
   auto sl = std::make_unique<Slot>();
   Slot &S = *sl;
   S.hp = std::move(hp);
@@ -466,6 +467,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
 }
 
 void slot_unload(Pool &P, int s) {
+  P.tile_epoch++;
   if (!P.slots[s]) return;
   Slot &S = *P.slots[s];
   if (S.task) {
@@ -809,6 +811,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   // groups
   std::vector<Group> groups;
   int64_t tpos = 0, ipos = 0;
+  const bool same_tiles = run == P.tiles_run && P.tiles_epoch == P.tile_epoch;
   size_t q = 0;
   while (q < run.size()) {
     size_t e = q;
@@ -832,7 +835,9 @@ static hallar_status run_round(Pool &P, bool &did_work) {
       Slot &S = *P.slots[s];
       g.slots.push_back(s);
       g.steps = std::max(g.steps, S.op.steps);
-      for (const Tile &t : S.hp.tiles) P.h_tiles[tpos++] = t;
+      if (same_tiles) tpos += (int64_t)S.hp.tiles.size();
+      else
+        for (const Tile &t : S.hp.tiles) P.h_tiles[tpos++] = t;
       P.h_ilist[ipos++] = s;
       g.maxm = std::max(g.maxm, S.hp.m);
       g.maxp = std::max<int>(g.maxp, (int)S.hp.npairs);
@@ -872,7 +877,11 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     P.insts_dirty = false;
   }
   HL_TRY(hipMemcpyAsync(P.d_prm, P.h_prm, sizeof(InstParams) * maxs, hipMemcpyHostToDevice, st), "upload params");
-  HL_TRY(hipMemcpyAsync(P.d_tiles, P.h_tiles, sizeof(Tile) * tpos, hipMemcpyHostToDevice, st), "upload tiles");
+  if (!same_tiles) {
+    HL_TRY(hipMemcpyAsync(P.d_tiles, P.h_tiles, sizeof(Tile) * tpos, hipMemcpyHostToDevice, st), "upload tiles");
+    P.tiles_run = run;
+    P.tiles_epoch = P.tile_epoch;
+  }
   HL_TRY(hipMemcpyAsync(P.d_ilist, P.h_ilist, sizeof(int32_t) * ipos, hipMemcpyHostToDevice, st), "upload ilist");
   if (up_used) HL_TRY(hipMemcpyAsync(P.d_up, P.h_up, sizeof(double) * up_used, hipMemcpyHostToDevice, st), "upload coef");
   if (groups.size() == 1) {

@@ -80,6 +80,11 @@ struct Pool {
   std::vector<InstDev> h_insts;
   Tile *d_tiles = nullptr, *h_tiles = nullptr;
   int64_t tiles_cap = 0;
+  // the slots whose tiles d_tiles holds, in order, and the load epoch they
+  // were taken at: a round with the same slots in the same order (a
+  // standalone solve, or a stable batch) skips rebuilding and uploading them
+  std::vector<int> tiles_run;
+  int64_t tile_epoch = 0, tiles_epoch = -1;
   int32_t *d_ilist = nullptr, *h_ilist = nullptr;
   int64_t ilist_cap = 0;
   double *d_up = nullptr, *h_up = nullptr;
