@@ -1510,31 +1510,38 @@ struct RedArgs {
   int32_t extra;  // number of constraint-major partial rows (general mode / set_p)
 };
 
-// Sums of slots [q0, q1) over partial rows [row0, row0 + nrows) into out[0..):
-// slots in batches of RQ; every thread adds rows t, t + blockDim, ... of each
-// slot of the batch (all loads of the batch in flight together), then a fixed
-// wave and cross-wave reduction -- a fixed order for every instance.
+// Sums of slots [q0, q1) and then [q2, q3) over partial rows [row0, row0 +
+// nrows) into out[0..): slots in batches of RQ; every thread adds rows t,
+// t + blockDim, ... of each slot of the batch (all loads of the batch in
+// flight together, the next row's issued before the current one is added),
+// then a fixed wave and cross-wave reduction -- a fixed order for every
+// instance, whichever batch a slot falls in.
 constexpr int RQ = 8;
-__device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nrows, double *out) {
+__device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nrows, double *out, int q2 = 0,
+                             int q3 = 0) {
   __shared__ double red[RBLOCK / 64][RQ];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int qb = q0; qb < q1; qb += RQ) {
-    const int nq = min(RQ, q1 - qb);
+  const int n1 = q1 - q0, ntot = n1 + (q3 - q2);
+  for (int qb = 0; qb < ntot; qb += RQ) {
+    const int nq = min(RQ, ntot - qb);
+    const double *src[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const int j = qb + u, q = j < n1 ? q0 + j : q2 + (j - n1);
+      src[u] = I.part + (size_t)(u < nq ? q : q0) * I.prows + row0;
+    }
     double s[RQ];
 #pragma unroll
     for (int u = 0; u < RQ; ++u) s[u] = 0.0;
-    const double *src = I.part + (size_t)qb * I.prows + row0;
-    // the loads of row t + blockDim.x are issued before row t is added, so
-    // each thread's rows cost one load latency each only when overlapped
     double cur[RQ];
     int t = tid;
 #pragma unroll
-    for (int u = 0; u < RQ; ++u) cur[u] = (u < nq && t < nrows) ? src[(size_t)u * I.prows + t] : 0.0;
+    for (int u = 0; u < RQ; ++u) cur[u] = (u < nq && t < nrows) ? src[u][t] : 0.0;
     for (; t < nrows; t += blockDim.x) {
       const int tn = t + blockDim.x;
       double nxt[RQ];
 #pragma unroll
-      for (int u = 0; u < RQ; ++u) nxt[u] = (u < nq && tn < nrows) ? src[(size_t)u * I.prows + tn] : 0.0;
+      for (int u = 0; u < RQ; ++u) nxt[u] = (u < nq && tn < nrows) ? src[u][tn] : 0.0;
 #pragma unroll
       for (int u = 0; u < RQ; ++u) s[u] += cur[u];
 #pragma unroll
@@ -1549,7 +1556,7 @@ __device__ void reduce_slots(const InstDev &I, int q0, int q1, int row0, int nro
     if (tid < nq) {
       double v = 0.0;
       for (int w = 0; w < nw; ++w) v += red[w][tid];
-      out[qb - q0 + tid] = v;
+      out[qb + tid] = v;
     }
     __syncthreads();
   }
@@ -1611,7 +1618,15 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     case RD_YP_PROJ:
     case RD_EVAL: {
       const int nlr = I.r0 * a.R;
-      reduce_slots(I, 0, 4 + nlr, 0, nt, S);
+      // the trial's second kernel's three slots ride in the same pass when
+      // they fit its batch
+      const int x0 = a.op == RD_TRIAL_FUSED ? FUSE_SLOT : (a.op == RD_YP_PROJ ? PROJ_SLOT : -1);
+      const bool one_pass = x0 >= 0 && 4 + nlr + 3 <= RQ;
+      if (one_pass) reduce_slots(I, 0, 4 + nlr, 0, nt, S, x0, x0 + 3);
+      else reduce_slots(I, 0, 4 + nlr, 0, nt, S);
+      double X3[3];
+      if (one_pass)
+        for (int q = 0; q < 3; ++q) X3[q] = S[4 + nlr + q];
       const int ex = I.direct ? 0 : (I.m + BLOCK - 1) / BLOCK;
       if (ex > 0) reduce_slots(I, 0, 3, nt, ex, E);
       else if (tid < 4) E[tid] = 0.0;
@@ -1634,22 +1649,21 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
         }
         if (!(g == g) || g - g != 0.0) res[S_NAN] = 1.0;
       }
-      if (a.op == RD_TRIAL_FUSED) {
+      if (x0 >= 0 && !one_pass) {
         __syncthreads();
-        reduce_slots(I, FUSE_SLOT, FUSE_SLOT + 3, 0, nt, S);  // FUSE_SLOT + 2 = COMBO_SLOT
-        if (tid == 0) {
-          res[S_NZ] = S[0];
-          res[S_PROJC] = S[0] > P.tau2 ? P.tau / sqrt(S[0]) : 1.0;
-          res[S_GR2T] = S[1];
-          res[S_XTW0] = S[2];
-        }
-      } else if (a.op == RD_YP_PROJ) {
-        __syncthreads();
-        reduce_slots(I, PROJ_SLOT, PROJ_SLOT + 3, 0, nt, S);
-        if (tid == 0) {
-          res[S_GR_D] = S[0];
-          res[S_D2] = S[1];
-          res[S_YPW0] = S[2];
+        reduce_slots(I, x0, x0 + 3, 0, nt, S);  // FUSE_SLOT + 2 = COMBO_SLOT
+        for (int q = 0; q < 3; ++q) X3[q] = S[q];
+      }
+      if (tid == 0) {
+        if (a.op == RD_TRIAL_FUSED) {
+          res[S_NZ] = X3[0];
+          res[S_PROJC] = X3[0] > P.tau2 ? P.tau / sqrt(X3[0]) : 1.0;
+          res[S_GR2T] = X3[1];
+          res[S_XTW0] = X3[2];
+        } else if (a.op == RD_YP_PROJ) {
+          res[S_GR_D] = X3[0];
+          res[S_D2] = X3[1];
+          res[S_YPW0] = X3[2];
         }
       }
       break;
