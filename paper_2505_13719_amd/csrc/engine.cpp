@@ -160,7 +160,8 @@ struct Carve {
 struct Layout {
   size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, low_pb, upb, b, K0, K064, D0, c_diag;
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
-  size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, gram, tiles, ilist;
+  size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
+      ilist;
   size_t total;
 };
 
@@ -216,6 +217,8 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.Z0 = c.take(2 * LR_MAX * R_MAX * 8);
   const size_t nt = hp.tiles.size();
   L.part = c.take(prows_for(hp) * PSTRIDE * 8);
+  L.red_stage = c.take(RED_SPLIT * 8 * 8);
+  L.red_count = c.take(4);
   L.gram = c.take(nt * (size_t)Rcap * Rcap * 8);
   L.tiles = c.take(nt * sizeof(Tile));
   L.ilist = c.take(sizeof(int32_t));
@@ -384,6 +387,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   put(base, L.ilist, il, st);
   if (h.m > 0) (void)hipMemsetAsync(base + L.p, 0, (size_t)h.m * 8, st);
   (void)hipMemsetAsync(base + L.Z0, 0, 2 * LR_MAX * R_MAX * 8, st);
+  (void)hipMemsetAsync(base + L.red_count, 0, 4, st);
   for (int q = 0; q < NBUF; ++q) (void)hipMemsetAsync(base + L.buf[q], 0, (size_t)h.n * S.Rcap * (f32 ? 4 : 8), st);
   if (hipStreamSynchronize(st) != hipSuccess) {
     err = "upload of the instance failed";
@@ -449,6 +453,8 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.up_base = P.d_up;
   D.dl_base = P.d_dl;
   D.part = (double *)at(L.part);
+  D.red_stage = (double *)at(L.red_stage);
+  D.red_count = (uint32_t *)at(L.red_count);
   D.gram = (double *)at(L.gram);
   D.prm = P.d_prm + s;
   D.res = P.d_res + s;

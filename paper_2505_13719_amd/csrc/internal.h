@@ -23,6 +23,7 @@ constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR
 constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos SpMV
 constexpr int LZ_WP_SLOT = PSTRIDE - 2;  // partial ||w'||^2 after the first Gram-Schmidt pass
 constexpr int LZ_KV_SLOT = PSTRIDE - 4;  // partial K0^T w' (LR_MAX slots)
+constexpr int RED_SPLIT = 16;            // workgroups per instance of the trial's reduces
 constexpr int FUSE_SLOT = PSTRIDE - 8;   // the fused trial kernel's SpMM partials (2 slots)
 constexpr int COMBO_SLOT = PSTRIDE - 6;  // the extrapolation's ||XT - W0||^2 partial
 constexpr int PROJ_SLOT = PSTRIDE - 12;  // the projection's three dot partials
@@ -142,6 +143,8 @@ struct InstDev {
   const double *up_base;                    // pool upload buffer (Ritz / restart coefficients, rotations)
   double *dl_base;                          // pool download buffer (Lanczos columns, Gram matrices)
   double *part;                             // PSTRIDE x prows partial sums, slot-major
+  double *red_stage;                        // RED_SPLIT x RQ sums of the split trial reduces
+  uint32_t *red_count;                      // blocks of a split reduce done (0 between launches)
   double *gram;                             // (R x R) x ntiles Gram partials, entry-major
   InstParams *prm;
   InstRes *res;

@@ -1594,7 +1594,39 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
   double *res = I.res->v;
   const int nt = I.ntiles;
   const int tid = threadIdx.x;
-  if (blockIdx.y > 0 && a.op != RD_LZ_H1 && a.op != RD_LZ_CHECKH2 && a.op != RD_GRAM) return;
+  // The trial's two reduces are split over RED_SPLIT workgroups per
+  // instance (one workgroup alone is bound by its own load latency over
+  // thousands of tile rows): workgroup y sums its contiguous share of the
+  // rows, writes its sums, and the workgroup that finishes last -- counted
+  // with one device-scope atomic, no waiting -- adds the RED_SPLIT rows in y
+  // order and goes on with the op.  The order of every sum is fixed.
+  const bool split = (a.op == RD_TRIAL_FUSED || a.op == RD_YP_PROJ) && gridDim.y == RED_SPLIT && I.direct &&
+                     4 + I.r0 * a.R + 3 <= RQ;
+  if (split) {
+    __shared__ int s_last;
+    const int nlr = I.r0 * a.R, nq = 4 + nlr + 3;
+    const int x0 = a.op == RD_TRIAL_FUSED ? FUSE_SLOT : PROJ_SLOT;
+    const int chunk = (nt + RED_SPLIT - 1) / RED_SPLIT;
+    const int y0 = blockIdx.y * chunk, y1 = min(nt, y0 + chunk);
+    reduce_slots(I, 0, 4 + nlr, y0, max(0, y1 - y0), S, x0, x0 + 3);
+    if (tid == 0) {
+      for (int q = 0; q < nq; ++q) I.red_stage[blockIdx.y * RQ + q] = S[q];
+      __threadfence();
+      s_last = atomicAdd(I.red_count, 1u) == RED_SPLIT - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (tid < nq) {
+      double v = 0.0;
+      for (int y = 0; y < RED_SPLIT; ++y) v += I.red_stage[y * RQ + tid];
+      S[tid] = v;
+    }
+    if (tid == 0) *I.red_count = 0u;  // every workgroup of this launch has counted
+    __syncthreads();
+  } else if (blockIdx.y > 0 && a.op != RD_LZ_H1 && a.op != RD_LZ_CHECKH2 && a.op != RD_GRAM) {
+    return;
+  }
   switch (a.op) {
     case RD_COMBO:
     case RD_NORM:
@@ -1622,8 +1654,13 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
       // they fit its batch
       const int x0 = a.op == RD_TRIAL_FUSED ? FUSE_SLOT : (a.op == RD_YP_PROJ ? PROJ_SLOT : -1);
       const bool one_pass = x0 >= 0 && 4 + nlr + 3 <= RQ;
-      if (one_pass) reduce_slots(I, 0, 4 + nlr, 0, nt, S, x0, x0 + 3);
-      else reduce_slots(I, 0, 4 + nlr, 0, nt, S);
+      if (split) {
+        // S holds the sums already
+      } else if (one_pass) {
+        reduce_slots(I, 0, 4 + nlr, 0, nt, S, x0, x0 + 3);
+      } else {
+        reduce_slots(I, 0, 4 + nlr, 0, nt, S);
+      }
       double X3[3];
       if (one_pass)
         for (int q = 0; q < 3; ++q) X3[q] = S[4 + nlr + q];
@@ -2051,6 +2088,7 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   RedArgs a{op, zsel, R, extra};
   int ny = 1;
   if (op == RD_LZ_H1 || op == RD_LZ_CHECKH2) ny = (KMAX + 1 + RQ - 1) / RQ;
+  else if (op == RD_TRIAL_FUSED || op == RD_YP_PROJ) ny = RED_SPLIT;
   else if (op == RD_GRAM) ny = (R * R + 63) / 64;
   hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
