@@ -150,7 +150,8 @@ def bench_solve(args):
     if args.precision:
         prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
     dev = torch.device("cuda:0")
-    opts = H.options(eps=1e-5, profile=1, time_limit=3000.0, verbose=args.verbose, autotune=args.autotune, **kw)
+    opts = H.options(eps=1e-5, profile=args.profile, time_limit=3000.0, verbose=args.verbose, autotune=args.autotune,
+                     **kw)
     t_build = time.perf_counter()
     h = H.hallar_create(prob, prec, opts)
     t_build = time.perf_counter() - t_build
@@ -215,7 +216,7 @@ def bench_served(args):
     reqs = [si.served_request(k, int(n), seed=5) for k, n in enumerate(sizes)]
     U0s = [si.gaussian_u0(int(n), 1000 + k) for k, n in enumerate(sizes)]
     t_gen = time.perf_counter() - t_gen
-    opts = H.options(eps=1e-5, profile=1, verbose=args.verbose)
+    opts = H.options(eps=1e-5, profile=args.profile, verbose=args.verbose)
     rate = args.rate
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq)) if rate > 0 else np.zeros(nreq)
     pool = H.hallar_pool_create(int(args.budget_gb * (1 << 30)), args.max_active, H.FP32_MIXED, opts)
@@ -346,6 +347,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0, help="solver progress on stderr (1: outer, 2: HLR)")
+    ap.add_argument("--profile", type=int, default=2, choices=[1, 2],
+                    help="HIP-event timing inside the timed solves: 2 = the sparse kernel classes only (default, "
+                         "least overhead), 1 = every class")
     ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
     ap.add_argument("--autotune", type=int, default=0, help="1: tune the tile schedule at create (timed outside the steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

@@ -100,7 +100,9 @@ typedef struct {
   double time_limit;                /* seconds per solve */
   uint64_t seed;                    /* Lanczos start vectors and default U0 */
   int32_t verbose;
-  int32_t profile;                  /* 1: time every kernel class with HIP events (see hallar_profile) */
+  int32_t profile;                  /* 1: time every kernel class with HIP events (see hallar_profile);
+                                       2: only the sparse classes (SDDMM, SpMM, fused trial, Lanczos
+                                       SpMV), for less event overhead; 0: off */
   int32_t autotune;                 /* 1: hallar_create times candidate tile schedules on the instance and
                                        keeps the fastest (see hallar_schedule); 0: the default schedule.
                                        The schedule fixes the order of the partial sums, so results of

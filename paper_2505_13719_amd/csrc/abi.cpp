@@ -45,6 +45,7 @@ bool check_opts(const hallar_options &o, std::string &msg) {
   if (o.eig_kmax < 0 || o.eig_kmax > hl::KMAX) { msg = "opts.eig_kmax must be in [0, 64]"; return false; }
   if (o.lower_gather != 0 && o.lower_gather != 1) { msg = "opts.lower_gather must be 0 or 1"; return false; }
   if (o.unfused_trial != 0 && o.unfused_trial != 1) { msg = "opts.unfused_trial must be 0 or 1"; return false; }
+  if (o.profile < 0 || o.profile > 2) { msg = "opts.profile must be 0, 1 or 2"; return false; }
   if (o.fista_max_iter < 1 || o.aipp_max_iter < 1 || o.hlr_max_iter < 1 || o.outer_max_iter < 1 || o.eig_max_iter < 1) {
     msg = "iteration caps must be >= 1";
     return false;
@@ -563,6 +564,10 @@ hallar_status hallar_pool_poll(hallar_pool_t pool, int64_t *tickets, hallar_resu
 
 static hallar_status profile_out(hl::Pool &P, double *ms, int64_t *launches, double *bytes, int32_t nc, int32_t reset) {
   if (nc < 0 || nc > hl::KC_N) return HALLAR_E_INVALID;
+  if (P.profile) {
+    if (hipStreamSynchronize(P.stream) != hipSuccess) return HALLAR_E_HIP;
+    hl::prof_flush(P);
+  }
   for (int c = 0; c < nc; ++c) {
     if (ms) ms[c] = P.prof_ms[c];
     if (launches) launches[c] = P.prof_n[c];

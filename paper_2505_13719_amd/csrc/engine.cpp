@@ -265,6 +265,7 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
   }
   HL_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming), "hipEventCreate");
   P.profile = opts.profile != 0;
+  P.prof_level = opts.profile;
   if (P.profile) {
     P.events.resize(8192);
     for (auto &ev : P.events) HL_TRY(hipEventCreate(&ev), "hipEventCreate");
@@ -516,7 +517,8 @@ struct ProfScope {
   double bytes;
   hipStream_t st;
   ProfScope(Pool &p, int c, double b, hipStream_t s) : P(p), cls(c), bytes(b), st(s) {
-    if (P.profile && P.ev_used + 2 <= (int)P.events.size()) {
+    const bool timed = P.prof_level == 1 || c == KC_SDDMM || c == KC_SPMM || c == KC_FUSED || c == KC_LZ_SPMV;
+    if (P.profile && timed && P.ev_used + 2 <= (int)P.events.size()) {
       e0 = P.ev_used;
       P.ev_used += 2;
       (void)hipEventRecord(P.events[e0], st);
@@ -530,7 +532,7 @@ struct ProfScope {
   }
 };
 
-static void prof_collect(Pool &P) {
+void prof_flush(Pool &P) {
   for (const ProfRec &r : P.recs) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, P.events[r.e0], P.events[r.e1]) == hipSuccess) {
@@ -608,9 +610,15 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     if (h.direct) max_pb = std::max<int64_t>(max_pb, h.npairs);
     if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
   }
+  // the trial's reduces are split over several workgroups per instance when
+  // every instance of the group has thousands of tiles (one workgroup then
+  // waits on its own loads); for small instances the split only adds work
+  int64_t min_tiles = INT64_MAX;
+  for (int s : g.slots) min_tiles = std::min<int64_t>(min_tiles, (int64_t)P.slots[s]->hp.tiles.size());
+  const int split = min_tiles >= 2048 ? 1 : 0;
   auto red = [&](int op, int zsel) {
     ProfScope ps(P, KC_REDUCE, 0.0, st);
-    op_reduce(st, IL, ni, D, op, zsel, R, 0);
+    op_reduce(st, IL, ni, D, op, zsel, R, (op == RDH_TRIAL_FUSED || op == RDH_YP_PROJ) ? split : 0);
   };
   auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
     {
@@ -912,7 +920,9 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   if (dl_used) HL_TRY(hipMemcpyAsync(P.h_dl, P.d_dl, sizeof(double) * dl_used, hipMemcpyDeviceToHost, st), "download");
   const double tr2 = now_s();
   HL_TRY(hipStreamSynchronize(st), "round");
-  if (P.profile) prof_collect(P);
+  // event times are read in batches, off most rounds' critical path (every
+  // event of a finished round is complete)
+  if (P.profile && P.ev_used + 512 > (int)P.events.size()) prof_flush(P);
   const double tr3 = now_s();
   P.rounds++;
   did_work = true;

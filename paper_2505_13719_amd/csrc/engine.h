@@ -98,6 +98,7 @@ struct Pool {
   hallar_status fatal = HALLAR_OK;
   // profiling (opts.profile)
   bool profile = false;
+  int prof_level = 0;  // 1: every kernel class, 2: the sparse streaming classes only
   std::vector<hipEvent_t> events;
   int ev_used = 0;
   std::vector<ProfRec> recs;
@@ -129,6 +130,8 @@ void slot_unload(Pool &P, int s);
 
 // solver: start the coroutine of slot s (U0: device FP64 n x r0 or NULL)
 void slot_start_solve(Pool &P, int s);
+// adds the elapsed times of the recorded, completed profiling events to the per-class totals
+void prof_flush(Pool &P);
 // run rounds until no slot has work or `max_rounds` rounds (<=0: unlimited)
 hallar_status pool_run(Pool &P, int max_rounds);
 int pool_active(const Pool &P);

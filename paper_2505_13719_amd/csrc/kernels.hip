@@ -1507,7 +1507,7 @@ struct RedArgs {
   int32_t op;
   int32_t zsel;
   int32_t R;      // current width (for K^T X slots / gram)
-  int32_t extra;  // number of constraint-major partial rows (general mode / set_p)
+  int32_t extra;  // RD_TRIAL_FUSED / RD_YP_PROJ: 1 = split over RED_SPLIT workgroups per instance
 };
 
 // Sums of slots [q0, q1) and then [q2, q3) over partial rows [row0, row0 +
@@ -2088,7 +2088,7 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   RedArgs a{op, zsel, R, extra};
   int ny = 1;
   if (op == RD_LZ_H1 || op == RD_LZ_CHECKH2) ny = (KMAX + 1 + RQ - 1) / RQ;
-  else if (op == RD_TRIAL_FUSED || op == RD_YP_PROJ) ny = RED_SPLIT;
+  else if ((op == RD_TRIAL_FUSED || op == RD_YP_PROJ) && extra) ny = RED_SPLIT;
   else if (op == RD_GRAM) ny = (R * R + 63) / 64;
   hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
