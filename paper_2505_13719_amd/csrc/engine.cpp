@@ -160,7 +160,7 @@ struct Carve {
 struct Layout {
   size_t rowptr_u, col_u, pcon, c_u, pa, c64, pa64, rowptr_l, col_l, pid_l, low_pb, upb, b, K0, K064, D0, c_diag;
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
-  size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
+  size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, m64_low, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
       ilist;
   size_t total;
 };
@@ -209,6 +209,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.TY = c.take(m * 8);
   L.Ty = c.take(m * 8);
   L.m64 = c.take(P * 8);
+  L.m64_low = c.take(nl * 8);
   L.V = c.take((size_t)(kmax + 1) * n * 8);
   L.V2 = c.take((size_t)(kmax + 1) * n * 8);
   L.w = c.take(n * 8);
@@ -445,6 +446,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.TY = (double *)at(L.TY);
   D.Ty = (double *)at(L.Ty);
   D.m64 = (double *)at(L.m64);
+  D.m64_low = (double *)at(L.m64_low);
   D.V = (double *)at(L.V);
   D.V2 = (double *)at(L.V2);
   D.w = (double *)at(L.w);
@@ -573,7 +575,7 @@ static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int 
     // row pointers, columns and {p_l, b_l}; the SpMM epilogue is added by
     // the caller
     b.fused += sd + (n + 1) * 4 + nl * 20;
-    b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 8 + 2 * (n + 1) * 4;
+    b.lz_spmv += n * 8 * 2 + Pp * (8 + 4) + nl * 12 + 2 * (n + 1) * 4;  // lower: column + lower-order value
     b.vec_n8 += n * 8;
   }
   return b;
@@ -597,6 +599,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   double msum = 0, psum = 0;
   bool any_lr = false;
   int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
+  int64_t max_nl = 0;
   // the trial's SDDMM and gradient SpMM run as one kernel when every instance
   // recomputes its lower half, has no low-rank objective term (its product
   // is reduced between the two) and the rows are narrow
@@ -609,6 +612,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     any_lr = any_lr || h.r0 > 0;
     if (h.direct) max_pb = std::max<int64_t>(max_pb, h.npairs);
     if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
+    max_nl = std::max<int64_t>(max_nl, h.nlower);
   }
   // the trial's reduces are split over several workgroups per instance when
   // every instance of the group has thousands of tiles (one workgroup then
@@ -697,6 +701,9 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         ProfScope ps(P, KC_OTHER, 0.0, st);
         if (dni > 0) op_pairvals(prec, st, DL, dni, g.maxp, D, 2, nullptr, 0);
         if (gni > 0) op_pairvals(prec, st, GL, gni, g.maxp, D, 2, nullptr, 1);
+        // the Lanczos matrix is fixed for the whole run: its lower half in
+        // lower order once, so every SpMV reads it contiguously
+        op_lower_copy(st, IL, ni, max_nl, D);
         op_lz_start(st, T, nt, D);
       }
       red(RDH_LZ_START, 0);

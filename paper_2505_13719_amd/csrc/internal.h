@@ -136,6 +136,7 @@ struct InstDev {
   double *Bpair;                            // general mode: <U_i,U_j> per pair
   double *p, *yp, *TY, *Ty;                 // length m
   double *m64;                              // pair values in FP64 (Lanczos)
+  double *m64_low;                          // the same values in lower order (copied once per Lanczos start)
   double *V, *V2;                           // Lanczos bases, (KMAX + 1) x n
   double *w, *lzv;                          // Lanczos work vector, Ritz / start vector
   double *hcoef;                            // KMAX + 1 reorthogonalisation coefficients

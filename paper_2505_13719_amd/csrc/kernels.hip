@@ -506,13 +506,15 @@ struct SpmmArgs {
 };
 
 // Stage a tile's entries of S u S^T into LDS: columns and pair values of the
-// upper CSR (coalesced), then the lower transpose, whose values are gathered
-// through the pair ids unless the caller recomputes them (lower_vals false:
-// columns only); SU entries per thread are loaded before any is stored, so
-// the gathers of a thread are in flight together.
+// upper CSR (coalesced), then the lower transpose, whose values come from a
+// lower-order copy (m_low, coalesced) or are gathered through the pair ids,
+// unless the caller recomputes them (lower_vals false: columns only); SU
+// entries per thread are loaded before any is stored, so the gathers of a
+// thread are in flight together.
 template <typename T>
 __device__ __forceinline__ void stage_entries(const InstDev &I, const T *__restrict__ m, int ku0, int nu, int kl0,
-                                              int nl, bool lower_vals, int32_t *s_col, T *s_m) {
+                                              int nl, bool lower_vals, int32_t *s_col, T *s_m,
+                                              const T *__restrict__ m_low = nullptr) {
   constexpr int SU = 8;
   for (int e0 = threadIdx.x; e0 < nu; e0 += BLOCK * SU) {
     int c[SU];
@@ -542,14 +544,14 @@ __device__ __forceinline__ void stage_entries(const InstDev &I, const T *__restr
       const int e = e0 + u * BLOCK;
       if (e < nl) {
         c[u] = I.col_l[kl0 + e];
-        if (lower_vals) id[u] = I.pid_l[kl0 + e];
+        if (lower_vals && !m_low) id[u] = I.pid_l[kl0 + e];
       }
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       const int e = e0 + u * BLOCK;
       v[u] = T(0);
-      if (lower_vals && e < nl) v[u] = m[id[u]];
+      if (lower_vals && e < nl) v[u] = m_low ? m_low[kl0 + e] : m[id[u]];
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
@@ -1245,6 +1247,14 @@ __global__ __launch_bounds__(BLOCK) void k_refresh_pb(const int32_t *__restrict_
   }
 }
 
+// FP64 pair values of the strictly-lower pairs in lower order (the Lanczos
+// matrix, fixed for a run).
+__global__ __launch_bounds__(BLOCK) void k_lower_copy(const int32_t *__restrict__ ilist,
+                                                      const InstDev *__restrict__ insts) {
+  const InstDev &I = insts[ilist[blockIdx.y]];
+  for (int e = blockIdx.x * BLOCK + threadIdx.x; e < I.nlower; e += gridDim.x * BLOCK) I.m64_low[e] = I.m64[I.pid_l[e]];
+}
+
 // ---------------------------------------------------------------------------
 // Lanczos (FP64).  Basis rows V[q * n + i]; w is the work vector.
 // ---------------------------------------------------------------------------
@@ -1315,7 +1325,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
   const int ku0 = s_ru[0], nu = s_ru[nrows] - ku0;
   const int kl0 = s_rl[0], nl = s_rl[nrows] - kl0;
   const bool staged = nu + nl <= TILE_MAX_ENTRIES;
-  if (staged) stage_entries<double>(I, I.m64, ku0, nu, kl0, nl, true, s_col, s_m);
+  if (staged) stage_entries<double>(I, I.m64, ku0, nu, kl0, nl, true, s_col, s_m, I.m64_low);
   const int plog = staged ? max(0, (int)tl.plog_s - 2) : (int)tl.plog_s;
   const int TS = 1 << plog;
   const int team = threadIdx.x >> plog;
@@ -1348,7 +1358,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
       }
     } else {
       for (int k = I.rowptr_u[i] + strm; k < I.rowptr_u[i + 1]; k += TS) w += I.m64[k] * v[I.col_u[k]];
-      for (int e = I.rowptr_l[i] + strm; e < I.rowptr_l[i + 1]; e += TS) w += I.m64[I.pid_l[e]] * v[I.col_l[e]];
+      for (int e = I.rowptr_l[i] + strm; e < I.rowptr_l[i + 1]; e += TS) w += I.m64_low[e] * v[I.col_l[e]];
     }
     for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
     if (strm == 0) {
@@ -2076,6 +2086,12 @@ void op_fw_den_gen(hipStream_t s, const int32_t *ilist, int ni, int maxm, const 
 void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d) {
   if (ni <= 0 || maxm <= 0) return;
   hipLaunchKernelGGL(k_set_p, dim3((maxm + BLOCK - 1) / BLOCK, ni), dim3(BLOCK), 0, s, ilist, d);
+}
+void op_lower_copy(hipStream_t s, const int32_t *ilist, int ni, int64_t maxnl, const InstDev *d) {
+  if (ni <= 0 || maxnl <= 0) return;
+  const int64_t nb = (maxnl + BLOCK - 1) / BLOCK;
+  const int gx = nb < 4096 ? (int)nb : 4096;
+  hipLaunchKernelGGL(k_lower_copy, dim3(gx, ni), dim3(BLOCK), 0, s, ilist, d);
 }
 void op_refresh_pb(hipStream_t s, const int32_t *ilist, int ni, int64_t maxcount, const InstDev *d) {
   if (ni <= 0 || maxcount <= 0) return;

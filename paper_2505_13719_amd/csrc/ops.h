@@ -41,6 +41,7 @@ void op_fw_den(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_fw_den_gen(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d);
 void op_set_p(hipStream_t s, const int32_t *ilist, int ni, int maxm, const InstDev *d);
 void op_refresh_pb(hipStream_t s, const int32_t *ilist, int ni, int64_t maxcount, const InstDev *d);
+void op_lower_copy(hipStream_t s, const int32_t *ilist, int ni, int64_t maxnl, const InstDev *d);
 void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int op, int zsel, int R, int extra);
 void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_lz_first(hipStream_t s, const Tile *t, int nt, const InstDev *d);
