@@ -513,6 +513,25 @@ struct Group {
 };
 
 // ------------------------------------------------------------------ profiling
+// Whether an instance's FISTA trials run as the fused kernel: a property of
+// the instance (and the pool's options) alone, and part of the grouping key,
+// so that an instance takes the same kernels -- and produces the same bits --
+// alone, in a batch or in the served mix.
+static bool trial_fuses(const Pool &P, int s) {
+  const HostProblem &h = P.slots[s]->hp;
+  return !P.opts.unfused_trial && h.direct && h.low_recompute && h.r0 == 0;
+}
+
+// grouping key of a slot's pending operation: packs are never merged (each
+// has its own source), trials of fused and unfused instances never are
+static int64_t group_key(const Pool &P, int s) {
+  const PendingOp &o = P.slots[s]->op;
+  int64_t k = o.key();
+  if (o.code == OP_PACK) k += (int64_t)s * 7919;
+  if (o.code == OP_TRIAL && trial_fuses(P, s)) k += 104729;
+  return k;
+}
+
 struct ProfScope {
   Pool &P;
   int cls, e0 = -1;
@@ -603,10 +622,10 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   // the trial's SDDMM and gradient SpMM run as one kernel when every instance
   // recomputes its lower half, has no low-rank objective term (its product
   // is reduced between the two) and the rows are narrow
-  bool fuse = !P.opts.unfused_trial && gni == 0 && trial_fusable(prec, R);
+  bool fuse = gni == 0 && trial_fusable(prec, R);
   for (int s : g.slots) {
     const HostProblem &h = P.slots[s]->hp;
-    fuse = fuse && h.direct && h.low_recompute && h.r0 == 0;
+    fuse = fuse && trial_fuses(P, s);
     msum += h.m;
     psum += (double)h.npairs;
     any_lr = any_lr || h.r0 > 0;
@@ -614,12 +633,13 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
     max_nl = std::max<int64_t>(max_nl, h.nlower);
   }
-  // the trial's reduces are split over several workgroups per instance when
-  // every instance of the group has thousands of tiles (one workgroup then
-  // waits on its own loads); for small instances the split only adds work
-  int64_t min_tiles = INT64_MAX;
-  for (int s : g.slots) min_tiles = std::min<int64_t>(min_tiles, (int64_t)P.slots[s]->hp.tiles.size());
-  const int split = min_tiles >= 2048 ? 1 : 0;
+  // the trial's reduces are split over several workgroups for instances with
+  // thousands of tiles (one workgroup then waits on its own loads); each
+  // instance decides by its own tile count, so the launch is split when any
+  // instance of the group is that large
+  int64_t max_tiles = 0;
+  for (int s : g.slots) max_tiles = std::max<int64_t>(max_tiles, (int64_t)P.slots[s]->hp.tiles.size());
+  const int split = max_tiles >= RED_SPLIT_MIN_TILES ? 1 : 0;
   auto red = [&](int op, int zsel) {
     ProfScope ps(P, KC_REDUCE, 0.0, st);
     op_reduce(st, IL, ni, D, op, zsel, R, (op == RDH_TRIAL_FUSED || op == RDH_YP_PROJ) ? split : 0);
@@ -803,12 +823,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     if (sp && sp->used && sp->has_op && !sp->done) ready.push_back(s);
   }
   if (ready.empty()) return HALLAR_OK;
-  std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) {
-    const PendingOp &x = P.slots[a]->op, &y = P.slots[b]->op;
-    const int kx = x.code == OP_PACK ? x.key() + a * 7919 : x.key();
-    const int ky = y.code == OP_PACK ? y.key() + b * 7919 : y.key();
-    return kx < ky;
-  });
+  std::stable_sort(ready.begin(), ready.end(), [&](int a, int b) { return group_key(P, a) < group_key(P, b); });
   int64_t up_used = 0, dl_used = 0, t_used = 0;
   std::vector<int> run;
   for (int s : ready) {
@@ -837,10 +852,10 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   while (q < run.size()) {
     size_t e = q;
     const PendingOp &o = P.slots[run[q]]->op;
-    const int k0 = o.code == OP_PACK ? o.key() + run[q] * 7919 : o.key();
+    const int64_t k0 = group_key(P, run[q]);
     while (e < run.size()) {
       const PendingOp &x = P.slots[run[e]]->op;
-      const int kx = x.code == OP_PACK ? x.key() + run[e] * 7919 : x.key();
+      const int64_t kx = group_key(P, run[e]);
       if (kx != k0) break;
       ++e;
     }

@@ -24,6 +24,7 @@ constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos S
 constexpr int LZ_WP_SLOT = PSTRIDE - 2;  // partial ||w'||^2 after the first Gram-Schmidt pass
 constexpr int LZ_KV_SLOT = PSTRIDE - 4;  // partial K0^T w' (LR_MAX slots)
 constexpr int RED_SPLIT = 16;            // workgroups per instance of the trial's reduces
+constexpr int RED_SPLIT_MIN_TILES = 2048;  // instances with fewer tiles reduce in one workgroup
 constexpr int FUSE_SLOT = PSTRIDE - 8;   // the fused trial kernel's SpMM partials (2 slots)
 constexpr int COMBO_SLOT = PSTRIDE - 6;  // the extrapolation's ||XT - W0||^2 partial
 constexpr int PROJ_SLOT = PSTRIDE - 12;  // the projection's three dot partials

@@ -1611,7 +1611,7 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
   // with one device-scope atomic, no waiting -- adds the RED_SPLIT rows in y
   // order and goes on with the op.  The order of every sum is fixed.
   const bool split = (a.op == RD_TRIAL_FUSED || a.op == RD_YP_PROJ) && gridDim.y == RED_SPLIT && I.direct &&
-                     4 + I.r0 * a.R + 3 <= RQ;
+                     4 + I.r0 * a.R + 3 <= RQ && nt >= RED_SPLIT_MIN_TILES;
   if (split) {
     __shared__ int s_last;
     const int nlr = I.r0 * a.R, nq = 4 + nlr + 3;

@@ -124,3 +124,34 @@ def test_large_batch_equals_alone():
         for k in KEYS:
             assert a[k] == b[k], (k, a[k], b[k])
     assert sum(a["status"] == "ok" for a in alone) >= len(probs) - 1
+
+
+def test_mixed_fused_batch_equals_alone():
+    """Instances whose FISTA trials run as the fused kernel (matrix
+    completion) batched with instances that take the separate kernels
+    (MaxCut, theta with its low-rank objective) at the same widths, and one
+    instance large enough (>= 2048 tiles) that its trial reduces are split
+    over several workgroups: every instance's result is bit-identical to its
+    solve alone (both choices are per instance)."""
+    d = dev()
+    rng = np.random.default_rng(21)
+    probs = [si.mc_planted(60, 90, 2, 2500, seed=6), si.mc_planted(40, 50, 2, 900, seed=2),
+             si.mc_planted(20000, 24000, 2, 2_400_000, seed=4)]
+    for n in (60, 200, 500):
+        i, j = si.er_edges(n, 6.0 / (n - 1), rng)
+        probs.append(si.maxcut_problem(n, i, j, si.pm1_weights(i.size, rng)))
+    probs.append(si.theta_problem(16, *si.hypercube_edges(4)))
+    prec = H.FP32_MIXED
+    alone = [_alone(p, prec) for p in probs]
+    hs = [H.hallar_create(p, prec, H.options(eps=1e-5)) for p in probs]
+    try:
+        assert H.hallar_schedule(hs[2])[2] >= 2048
+        U0s = [torch.tensor(si.gaussian_u0(p.n, 3), device=d) for p in probs]
+        batch = H.hallar_solve_batch(hs, U0s)
+    finally:
+        for h in hs:
+            H.hallar_destroy(h)
+    for a, b in zip(alone, batch):
+        assert a["status"] == "ok", a
+        for k in KEYS:
+            assert a[k] == b[k], (k, a[k], b[k])
