@@ -207,6 +207,28 @@ hallar_status hallar_get_solution(hallar_t h, double *U, int64_t ldu, double *p,
 hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *const *U0s,
                                  hallar_result *results);
 
+/* Host-side structure of an instance (Section 4.1: the union support S and
+ * the symmetric pattern S u S^T), computed without a GPU.  tile_row0, when
+ * not NULL, receives the first row of each tile of the default schedule plus
+ * n at the end (min(tiles + 1, cap) entries written); the schedule's tiles
+ * hold at most 1024 rows and 2048 entries of S u S^T (a longer row is a tile
+ * of its own), and a tile closed by the entry cap has a power-of-two row
+ * count when it has 4 to 128 rows.  E_INVALID / E_UNSUPPORTED /
+ * E_NUMERICAL as for hallar_create; NULL out gives E_INVALID. */
+typedef struct {
+  int64_t pairs;            /* |S|: upper-triangle pairs with an objective or constraint entry */
+  int64_t lower;            /* strictly-lower entries of S u S^T */
+  int64_t tiles;            /* tiles of the default schedule */
+  int32_t direct;           /* every constraint has one pair, every pair at most one constraint */
+  int32_t con_rule;         /* direct mode: 1 if exactly the off-diagonal pairs are constrained,
+                               2 if exactly the diagonal ones are, 0 otherwise */
+  int32_t lower_recompute;  /* every strictly-lower pair is constrained with one shared coefficient
+                               and has no sparse objective entry (see opts.lower_gather) */
+  int32_t pad_;
+} hallar_structure;
+
+hallar_status hallar_inspect(const hallar_problem *prob, hallar_structure *out, int64_t *tile_row0, int64_t cap);
+
 /* ---- serving pool: continuous batching with HBM-footprint admission ---- */
 
 /* Device bytes an instance would hold in a pool (problem data + solver

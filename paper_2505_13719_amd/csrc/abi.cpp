@@ -474,6 +474,27 @@ hallar_status hallar_footprint(const hallar_problem *prob, hallar_precision prec
   return HALLAR_OK;
 }
 
+hallar_status hallar_inspect(const hallar_problem *prob, hallar_structure *out, int64_t *tile_row0, int64_t cap) {
+  if (!out) return fail(nullptr, HALLAR_E_INVALID, "out is NULL");
+  hl::HostProblem hp;
+  hallar_status code;
+  std::string msg = hl::build_host_problem(prob, hp, &code);
+  if (code != HALLAR_OK) return fail(nullptr, code, msg);
+  out->pairs = hp.npairs;
+  out->lower = hp.nlower;
+  out->tiles = (int64_t)hp.tiles.size();
+  out->direct = hp.direct ? 1 : 0;
+  out->con_rule = hp.direct ? hp.con_rule : 0;
+  out->lower_recompute = hp.low_recompute ? 1 : 0;
+  out->pad_ = 0;
+  if (tile_row0) {
+    const int64_t nt = (int64_t)hp.tiles.size();
+    for (int64_t t = 0; t < nt && t < cap; ++t) tile_row0[t] = hp.tiles[t].row0;
+    if (nt < cap) tile_row0[nt] = hp.n;
+  }
+  return HALLAR_OK;
+}
+
 hallar_status hallar_pool_create(size_t hbm_budget, int32_t max_active, hallar_precision prec, const hallar_options *opts,
                                  void *stream, hallar_pool_t *out) {
   if (!out || max_active < 1 || hbm_budget < 4096) return fail(nullptr, HALLAR_E_INVALID, "bad pool arguments");

@@ -67,7 +67,7 @@ EXPORTS = ["hallar_default_options", "hallar_create", "hallar_destroy", "hallar_
            "hallar_eval_AUUt", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
            "hallar_solve_batch", "hallar_footprint", "hallar_pool_create", "hallar_pool_destroy",
            "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage", "hallar_profile",
-           "hallar_pool_profile", "hallar_schedule"]
+           "hallar_pool_profile", "hallar_schedule", "hallar_inspect"]
 
 _lib = None
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.hallar_get_solution.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.hallar_solve_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(hallar_result)]
     L.hallar_footprint.argtypes = [C.POINTER(hallar_problem), C.c_int, C.POINTER(hallar_options), C.POINTER(C.c_size_t)]
+    L.hallar_inspect.argtypes = [C.POINTER(hallar_problem), C.POINTER(hallar_structure), i64p, C.c_int64]
     L.hallar_pool_create.argtypes = [C.c_size_t, C.c_int32, C.c_int, C.POINTER(hallar_options), vp, C.POINTER(vp)]
     L.hallar_pool_destroy.argtypes = [vp]
     L.hallar_pool_admit.argtypes = [vp, C.POINTER(hallar_problem), vp, C.c_int64]
@@ -308,6 +309,24 @@ def hallar_solve_batch(handles, U0s=None):
     res = (hallar_result * n)()
     _check(load().hallar_solve_batch(arr, n, u0, res))
     return [r.as_dict() for r in res]
+
+
+class hallar_structure(C.Structure):
+    _fields_ = [("pairs", C.c_int64), ("lower", C.c_int64), ("tiles", C.c_int64), ("direct", C.c_int32),
+                ("con_rule", C.c_int32), ("lower_recompute", C.c_int32), ("pad_", C.c_int32)]
+
+
+def hallar_inspect(prob):
+    """Host-side structure of an instance (no GPU): pair counts, mode flags and
+    the default tile schedule's first rows (numpy int64, tiles + 1 entries)."""
+    pa = _ProblemArrays(prob)
+    out = hallar_structure()
+    _check(load().hallar_inspect(C.byref(pa.c), C.byref(out), None, 0))
+    rows = np.zeros(out.tiles + 1, dtype=np.int64)
+    _check(load().hallar_inspect(C.byref(pa.c), C.byref(out), rows.ctypes.data_as(i64p), rows.size))
+    d = {k: getattr(out, k) for k, _ in out._fields_ if k != "pad_"}
+    d["tile_row0"] = rows
+    return d
 
 
 def hallar_footprint(prob, precision=FP64, opts=None):
