@@ -922,14 +922,25 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
 // ---------------------------------------------------------------------------
 // Vector kernels over the rows of a tile (G chunks per row).
 // ---------------------------------------------------------------------------
+// The trial's two vector kernels stream a few bytes per row: a workgroup
+// takes VT tiles at once, VL lanes each (strided over the tile's chunks),
+// and each tile's partial sums are formed by a butterfly inside its VL lanes
+// -- no LDS, no barrier, and VT times fewer workgroups than tiles.
+constexpr int VT = 16;
+constexpr int VL = BLOCK / VT;
+static_assert(VL <= 64 && (VL & (VL - 1)) == 0, "a tile's lanes sit inside one wave");
+
 // FISTA extrapolation: optionally X <- u1 Y + u2 X + u3 XT (x_{i+1} of the
 // previous accepted trial, Y = y_{i+1}, s = (L - mu)(x~ - y+) folded in), then
 // XT = cY Y + cX X; partial ||XT - W0||^2.
 template <typename T, int G>
-__global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+__global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                 int nt) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[tile_index()];
+  const int tix = blockIdx.x * VT + threadIdx.x / VL, sl = threadIdx.x % VL;
+  if (tix >= nt) return;  // whole VL-lane groups leave together
+  const Tile tl = tiles[tix];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   const T *Xp = role_ptr<T>(I, P, RX);
@@ -939,10 +950,10 @@ __global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles,
   const T *W0p = role_ptr<T>(I, P, RW0);
   const T cY = (T)P.cY, cX = (T)P.cX, u1 = (T)P.u1, u2 = (T)P.u2, u3 = (T)P.u3;
   const int upd = P.upd_x;
-  double acc[1] = {0.0};
+  double acc = 0.0;
   const int total = (tl.row1 - tl.row0) * G;
   const size_t base = (size_t)tl.row0 * R;
-  for (int t = threadIdx.x; t < total; t += BLOCK) {
+  for (int t = sl; t < total; t += VL) {
     const size_t off = base + (size_t)t * NC;
     Chunk<T> x = ldc(Xp + off);
     const Chunk<T> y = ldc(Yp + off), w0 = ldc(W0p + off);
@@ -957,20 +968,24 @@ __global__ __launch_bounds__(BLOCK) void k_combo(const Tile *__restrict__ tiles,
     for (int e = 0; e < NC; ++e) {
       o.v[e] = cY * y.v[e] + cX * x.v[e];
       const double d = (double)o.v[e] - (double)w0.v[e];
-      acc[0] += d * d;
+      acc += d * d;
     }
     stc(XTp + off, o);
   }
-  block_partials<1, COMBO_SLOT>(acc, I, tl.lt);
+  acc = group_sum<VL>(acc);
+  if (sl == 0) I.part[(size_t)COMBO_SLOT * I.prows + tl.lt] = acc;
 }
 
 // y+ = c Z (projection onto the Frobenius ball, c from the reduce kernel),
 // partials <GR, y+ - XT>, ||y+ - XT||^2, ||y+ - W0||^2.
 template <typename T, int G>
-__global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+__global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                int nt) {
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  const Tile tl = tiles[tile_index()];
+  const int tix = blockIdx.x * VT + threadIdx.x / VL, sl = threadIdx.x % VL;
+  if (tix >= nt) return;
+  const Tile tl = tiles[tix];
   const InstDev &I = insts[tl.inst];
   const InstParams &P = *I.prm;
   T *Zp = role_ptr<T>(I, P, RZ);
@@ -981,7 +996,7 @@ __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, 
   double acc[3] = {0.0, 0.0, 0.0};
   const int total = (tl.row1 - tl.row0) * G;
   const size_t base = (size_t)tl.row0 * R;
-  for (int t = threadIdx.x; t < total; t += BLOCK) {
+  for (int t = sl; t < total; t += VL) {
     const size_t off = base + (size_t)t * NC;
     Chunk<T> z = ldc(Zp + off);
     const Chunk<T> xt = ldc(XTp + off), gr = ldc(GRp + off), w0 = ldc(W0p + off);
@@ -996,7 +1011,11 @@ __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, 
     }
     stc(Zp + off, z);
   }
-  block_partials<3, PROJ_SLOT>(acc, I, tl.lt);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double v = group_sum<VL>(acc[q]);
+    if (sl == 0) I.part[(size_t)(PROJ_SLOT + q) * I.prows + tl.lt] = v;
+  }
 }
 
 // Copy role src -> role dst (scaled), optional partial ||dst||^2.
@@ -1876,11 +1895,11 @@ static void l_spmm(hipStream_t s, const Tile *t, int nt, const InstDev *d, SpmmA
 }
 template <typename T, int G>
 static void l_combo(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  hipLaunchKernelGGL((k_combo<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
+  hipLaunchKernelGGL((k_combo<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
 }
 template <typename T, int G>
 static void l_proj(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  hipLaunchKernelGGL((k_proj<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
+  hipLaunchKernelGGL((k_proj<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
 }
 template <typename T, int G>
 static void l_copy(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
