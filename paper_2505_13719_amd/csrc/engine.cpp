@@ -918,7 +918,10 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     P.tiles_run = run;
     P.tiles_epoch = P.tile_epoch;
   }
-  HL_TRY(hipMemcpyAsync(P.d_ilist, P.h_ilist, sizeof(int32_t) * ipos, hipMemcpyHostToDevice, st), "upload ilist");
+  if ((int64_t)P.ilist_dev.size() != ipos || !std::equal(P.ilist_dev.begin(), P.ilist_dev.end(), P.h_ilist)) {
+    HL_TRY(hipMemcpyAsync(P.d_ilist, P.h_ilist, sizeof(int32_t) * ipos, hipMemcpyHostToDevice, st), "upload ilist");
+    P.ilist_dev.assign(P.h_ilist, P.h_ilist + ipos);
+  }
   if (up_used) HL_TRY(hipMemcpyAsync(P.d_up, P.h_up, sizeof(double) * up_used, hipMemcpyHostToDevice, st), "upload coef");
   if (groups.size() == 1) {
     launch_group(P, groups[0], st);

@@ -84,6 +84,7 @@ struct Pool {
   // were taken at: a round with the same slots in the same order (a
   // standalone solve, or a stable batch) skips rebuilding and uploading them
   std::vector<int> tiles_run;
+  std::vector<int32_t> ilist_dev;  // the instance lists d_ilist holds (a round with the same lists skips the upload)
   int64_t tile_epoch = 0, tiles_epoch = -1;
   int32_t *d_ilist = nullptr, *h_ilist = nullptr;
   int64_t ilist_cap = 0;
