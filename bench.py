@@ -361,7 +361,7 @@ def main():
                     help="served: also solve this many requests one at a time with the plain FP64 solver")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "ops":

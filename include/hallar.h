@@ -43,7 +43,7 @@ typedef struct hallar_pool_s *hallar_pool_t;
 typedef enum {
   HALLAR_OK = 0,
   HALLAR_E_INVALID = 1,        /* bad argument, shape or index (i > j, l > m, ...) */
-  HALLAR_E_UNSUPPORTED = 2,    /* valid input outside what this build implements */
+  HALLAR_E_UNSUPPORTED = 2,    /* valid input outside what the library implements */
   HALLAR_E_OOM = 3,            /* device memory / pool budget exhausted */
   HALLAR_E_HIP = 4,            /* a HIP runtime call failed */
   HALLAR_E_NOT_CONVERGED = 5,  /* eigen solve stopped above its tolerance */
@@ -67,7 +67,7 @@ typedef enum { HALLAR_FP64 = 0, HALLAR_FP32_MIXED = 1 } hallar_precision;
  * (row, col, con) triples are summed.  Low-rank part: n_lowrank terms; term t
  * adds K_t D_t K_t^T to A_{lr_con[t]}, K_t is n x lr_rank[t] row-major at
  * K + K_off[t], D_t is lr_rank[t] x lr_rank[t] row-major at D + D_off[t].
- * This build supports low-rank terms on the objective only (lr_con = 0,
+ * The library supports low-rank terms on the objective only (lr_con = 0,
  * at most one term, rank <= 2); others give HALLAR_E_UNSUPPORTED. */
 typedef struct {
   int64_t n;             /* X is n x n, 1 <= n < 2^31 */

@@ -61,7 +61,7 @@ def test_descriptor_validation():
     q = si.random_hslr(8, 4, 0)
     q.val = q.val.copy(); q.val[3] = np.nan
     _bad(q, 9)
-    # low-rank term on a constraint: unsupported in this build
+    # low-rank term on a constraint: unsupported by the library
     q = si.random_hslr(8, 4, 0, lowrank_nonobjective=True)
     _bad(q, 2)
     # a valid one has a positive, deterministic footprint
