@@ -139,6 +139,24 @@ def cpu_baseline(prob, res, budget_s=20.0):
                 est_seconds=round(est, 1))
 
 
+def copy_peak_gbs(reps=5):
+    """Achievable HBM rate on this GPU: a plain 1 GiB device copy (read + write),
+    timed with events after a warm-up copy."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return round(2 * (1 << 30) / sec / 1e9, 1)
+
+
 def bench_solve(args):
     import numpy as np  # noqa: F401
     import torch
@@ -175,6 +193,9 @@ def bench_solve(args):
     roof, table = roofline_from_profile(prof)
     if roof:
         roof["traffic"] = counted_traffic(args.workload, roof["kernel"])
+        # the same achieved rate against what a plain copy reaches here
+        roof["copy_gbs"] = copy_peak_gbs()
+        roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
     out = {
         "metric": "SDP solves/s at 1e-5 rel gap",
         "value": round(args.steps / dt, 6),
