@@ -61,7 +61,7 @@ __device__ __forceinline__ double chunk_dot(const Chunk<T> &a, const Chunk<T> &b
   return d;
 }
 
-// Augmented-Lagrangian terms of one constrained pair (Section 3: the
+// Augmented-Lagrangian terms of one constrained pair (Section 2, eq. AL function: the
 // multiplier estimate inside the gradient of the augmented Lagrangian):
 // t = (2 - delta_ij) a B, r = t - b_l, y' = p_l + beta r and the pair value
 // m = c + a y'.  Contraction is off and the fused steps are explicit, so the
@@ -796,7 +796,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
   if (MODE != SP_PLAIN) block_partials<NQ>(acc, I, tl.lt);
 }
 
-// FISTA trial point (Section 3.2, ADAP-FISTA): the SDDMM at XT and the
+// FISTA trial point (Appendix A.1, ADAP-FISTA): the SDDMM at XT and the
 // gradient SpMM at XT in one pass, for direct instances whose lower half is
 // recomputed, with no low-rank objective term and narrow rows (G <= 2).  The
 // row walk of the SpMM recomputes every entry's value from the two factor
