@@ -853,12 +853,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     size_t e = q;
     const PendingOp &o = P.slots[run[q]]->op;
     const int64_t k0 = group_key(P, run[q]);
-    while (e < run.size()) {
-      const PendingOp &x = P.slots[run[e]]->op;
-      const int64_t kx = group_key(P, run[e]);
-      if (kx != k0) break;
-      ++e;
-    }
+    while (e < run.size() && group_key(P, run[e]) == k0) ++e;
     Group g{};
     g.code = o.code;
     g.R = o.R;
