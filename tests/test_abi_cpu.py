@@ -75,3 +75,15 @@ def test_footprint_grows_with_size():
     small = si.maxcut_problem(50, *si.er_edges(50, 0.1, np.random.default_rng(0)))
     big = si.maxcut_problem(500, *si.er_edges(500, 0.1, np.random.default_rng(0)))
     assert H.hallar_footprint(big) > H.hallar_footprint(small)
+
+
+@pytest.mark.parametrize("field,value", [("lower_gather", 2), ("unfused_trial", -1), ("profile", 3),
+                                         ("rank_cap", 65), ("eig_kmax", 65), ("sigma", 0.6)])
+def test_option_validation(field, value):
+    """hallar_create checks the options before touching the device: an out-of-range
+    value gives E_INVALID naming the field."""
+    o = H.options(**{field: value})
+    with pytest.raises(H.HallarError) as e:
+        H.hallar_create(si.random_hslr(8, 4, 0), H.FP64, o, stream=0)  # no device is touched
+    assert e.value.status == 1
+    assert field in str(e.value)
