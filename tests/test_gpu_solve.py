@@ -230,3 +230,29 @@ def test_lower_recompute_and_fusion_bitwise(name, maker, prec, r0, fused):
         assert nf > 0
     elif fused is False:
         assert nf == 0
+
+
+def test_profile_levels():
+    """opts.profile = 1 times every kernel class, 2 only the sparse ones (SDDMM,
+    SpMM, fused trial, Lanczos SpMV), 0 none; the solve is the same at every
+    level (the events do not touch the data)."""
+    d = dev()
+    prob = si.mc_planted(300, 400, 2, 20000, seed=8)
+    out = {}
+    for level in (0, 1, 2):
+        h = H.hallar_create(prob, H.FP32_MIXED, H.options(eps=1e-5, profile=level))
+        try:
+            res = H.hallar_solve(h, torch.tensor(si.gaussian_u0(prob.n, 7), device=d))
+            out[level] = (res, H.hallar_profile(h))
+        finally:
+            H.hallar_destroy(h)
+    sparse = ("sddmm", "spmm", "lanczos_spmv", "sddmm_spmm")
+    for k, v in out[0][1].items():
+        assert v["launches"] == 0 and v["ms"] == 0.0, k
+    assert all(out[1][1][k]["launches"] > 0 for k in ("vector", "reduce", "sddmm_spmm"))
+    for k, v in out[2][1].items():
+        if k in sparse:
+            assert v["launches"] == out[1][1][k]["launches"], k
+        else:
+            assert v["launches"] == 0, k
+    assert out[0][0]["pval"] == out[1][0]["pval"] == out[2][0]["pval"]
