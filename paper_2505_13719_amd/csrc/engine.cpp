@@ -618,7 +618,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   double msum = 0, psum = 0;
   bool any_lr = false;
   int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
-  int64_t max_nl = 0;
+  int64_t max_nl = 0, nrows = 0;
   // the trial's SDDMM and gradient SpMM run as one kernel when every instance
   // recomputes its lower half, has no low-rank objective term (its product
   // is reduced between the two) and the rows are narrow
@@ -632,6 +632,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     if (h.direct) max_pb = std::max<int64_t>(max_pb, h.npairs);
     if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
     max_nl = std::max<int64_t>(max_nl, h.nlower);
+    nrows += h.n;
   }
   // the trial's reduces are split over several workgroups for instances with
   // thousands of tiles (one workgroup then waits on its own loads); each
@@ -660,7 +661,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     case OP_TRIAL:
       {
         ProfScope ps(P, KC_VEC, 4 * B.urow, st);
-        op_combo(prec, R, st, T, nt, D);
+        op_combo(prec, R, st, T, nt, D, nrows);
       }
       // partial sums go to disjoint slots so that one reduce serves several
       // kernels: the extrapolation's with the fused trial's, the
@@ -682,7 +683,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       }
       {
         ProfScope ps(P, KC_VEC, 5 * B.urow, st);
-        op_proj(prec, R, st, T, nt, D);
+        op_proj(prec, R, st, T, nt, D, nrows);
       }
       // the AL value at y+ only: the pair values there are needed by the
       // gradient at the accepted trial, which forms them itself (OP_GRAD)

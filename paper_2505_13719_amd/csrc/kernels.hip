@@ -922,10 +922,12 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
 // ---------------------------------------------------------------------------
 // Vector kernels over the rows of a tile (G chunks per row).
 // ---------------------------------------------------------------------------
-// The trial's two vector kernels stream a few bytes per row: a workgroup
-// takes VT tiles at once, VL lanes each (strided over the tile's chunks),
-// and each tile's partial sums are formed by a butterfly inside its VL lanes
-// -- no LDS, no barrier, and VT times fewer workgroups than tiles.
+// The trial's two vector kernels stream a few bytes per row.  For tiles of
+// few chunks (the short tiles of long rows) a workgroup takes VT tiles at
+// once, VL lanes each (strided over the tile's chunks), and each tile's
+// partial sums are formed by a butterfly inside its VL lanes -- no LDS, no
+// barrier, and VT times fewer workgroups than tiles; tiles of many chunks
+// take one workgroup each (k_combo_tile, k_proj_tile below).
 constexpr int VT = 16;
 constexpr int VL = BLOCK / VT;
 static_assert(VL <= 64 && (VL & (VL - 1)) == 0, "a tile's lanes sit inside one wave");
@@ -1016,6 +1018,83 @@ __global__ __launch_bounds__(BLOCK) void k_proj(const Tile *__restrict__ tiles, 
     const double v = group_sum<VL>(acc[q]);
     if (sl == 0) I.part[(size_t)(PROJ_SLOT + q) * I.prows + tl.lt] = v;
   }
+}
+
+// The same two steps with one workgroup per tile, for tiles of many chunks
+// (long row ranges or wide rows), where sixteen lanes per tile would leave
+// the chip short of loads in flight.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_combo_tile(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[tile_index()];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  const T *Xp = role_ptr<T>(I, P, RX);
+  T *XNp = role_ptr<T>(I, P, RU2);  // updated x (a different buffer than RX)
+  const T *Yp = role_ptr<T>(I, P, RY);
+  T *XTp = role_ptr<T>(I, P, RXT);
+  const T *W0p = role_ptr<T>(I, P, RW0);
+  const T cY = (T)P.cY, cX = (T)P.cX, u1 = (T)P.u1, u2 = (T)P.u2, u3 = (T)P.u3;
+  const int upd = P.upd_x;
+  double acc[1] = {0.0};
+  const int total = (tl.row1 - tl.row0) * G;
+  const size_t base = (size_t)tl.row0 * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const size_t off = base + (size_t)t * NC;
+    Chunk<T> x = ldc(Xp + off);
+    const Chunk<T> y = ldc(Yp + off), w0 = ldc(W0p + off);
+    if (upd) {
+      const Chunk<T> xt = ldc(XTp + off);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) x.v[e] = u1 * y.v[e] + u2 * x.v[e] + u3 * xt.v[e];
+      stc(XNp + off, x);
+    }
+    Chunk<T> o;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      o.v[e] = cY * y.v[e] + cX * x.v[e];
+      const double d = (double)o.v[e] - (double)w0.v[e];
+      acc[0] += d * d;
+    }
+    stc(XTp + off, o);
+  }
+  block_partials<1, COMBO_SLOT>(acc, I, tl.lt);
+}
+
+// y+ = c Z (projection onto the Frobenius ball, c from the reduce kernel),
+// partials <GR, y+ - XT>, ||y+ - XT||^2, ||y+ - W0||^2.
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_proj_tile(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[tile_index()];
+  const InstDev &I = insts[tl.inst];
+  const InstParams &P = *I.prm;
+  T *Zp = role_ptr<T>(I, P, RZ);
+  const T *XTp = role_ptr<T>(I, P, RXT);
+  const T *GRp = role_ptr<T>(I, P, RGR);
+  const T *W0p = role_ptr<T>(I, P, RW0);
+  const T c = (T)I.res->v[S_PROJC];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int total = (tl.row1 - tl.row0) * G;
+  const size_t base = (size_t)tl.row0 * R;
+  for (int t = threadIdx.x; t < total; t += BLOCK) {
+    const size_t off = base + (size_t)t * NC;
+    Chunk<T> z = ldc(Zp + off);
+    const Chunk<T> xt = ldc(XTp + off), gr = ldc(GRp + off), w0 = ldc(W0p + off);
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      z.v[e] = c * z.v[e];
+      const double d = (double)z.v[e] - (double)xt.v[e];
+      const double f = (double)z.v[e] - (double)w0.v[e];
+      acc[0] += (double)gr.v[e] * d;
+      acc[1] += d * d;
+      acc[2] += f * f;
+    }
+    stc(Zp + off, z);
+  }
+  block_partials<3, PROJ_SLOT>(acc, I, tl.lt);
 }
 
 // Copy role src -> role dst (scaled), optional partial ||dst||^2.
@@ -1894,12 +1973,14 @@ static void l_spmm(hipStream_t s, const Tile *t, int nt, const InstDev *d, SpmmA
   else hipLaunchKernelGGL((k_spmm<T, G, SP_AIPP>), dim3(nt), dim3(BLOCK), 0, s, t, d, a);
 }
 template <typename T, int G>
-static void l_combo(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  hipLaunchKernelGGL((k_combo<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
+static void l_combo(hipStream_t s, const Tile *t, int nt, const InstDev *d, bool grouped) {
+  if (grouped) hipLaunchKernelGGL((k_combo<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
+  else hipLaunchKernelGGL((k_combo_tile<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
 }
 template <typename T, int G>
-static void l_proj(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  hipLaunchKernelGGL((k_proj<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
+static void l_proj(hipStream_t s, const Tile *t, int nt, const InstDev *d, bool grouped) {
+  if (grouped) hipLaunchKernelGGL((k_proj<T, G>), dim3((nt + VT - 1) / VT), dim3(BLOCK), 0, s, t, d, nt);
+  else hipLaunchKernelGGL((k_proj_tile<T, G>), dim3(nt), dim3(BLOCK), 0, s, t, d);
 }
 template <typename T, int G>
 static void l_copy(hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
@@ -1953,15 +2034,22 @@ void op_trial_fused(int prec, int R, hipStream_t s, const Tile *t, int nt, const
     else if (G == 2) hipLaunchKernelGGL((k_trial_fused<float, 2>), dim3(nt), dim3(BLOCK), 0, s, t, d, xrole);
   }
 }
-void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d) {
-  if (nt <= 0) return;
-  if (is64(prec)) HL_DISPATCH_G(double, R, l_combo, s, t, nt, d);
-  else HL_DISPATCH_G(float, R, l_combo, s, t, nt, d);
+// tiles of at most 64 chunks on average take the grouped vector kernels
+static bool vec_grouped(int prec, int R, int nt, int64_t rows) {
+  const int G = is64(prec) ? g_of<double>(R) : g_of<float>(R);
+  return rows * G <= (int64_t)64 * nt;
 }
-void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d) {
+void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int64_t rows) {
   if (nt <= 0) return;
-  if (is64(prec)) HL_DISPATCH_G(double, R, l_proj, s, t, nt, d);
-  else HL_DISPATCH_G(float, R, l_proj, s, t, nt, d);
+  const bool gr = vec_grouped(prec, R, nt, rows);
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_combo, s, t, nt, d, gr);
+  else HL_DISPATCH_G(float, R, l_combo, s, t, nt, d, gr);
+}
+void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int64_t rows) {
+  if (nt <= 0) return;
+  const bool gr = vec_grouped(prec, R, nt, rows);
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_proj, s, t, nt, d, gr);
+  else HL_DISPATCH_G(float, R, l_proj, s, t, nt, d, gr);
 }
 void op_copy_scale(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst) {
   if (nt <= 0) return;

@@ -17,11 +17,12 @@ void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstD
 void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);
 void op_spmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int zsel,
              int outrole, int mode);
-void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
+// rows: total rows of the launch's instances (chooses the grouped or per-tile form)
+void op_combo(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int64_t rows);
 // SDDMM + gradient SpMM at the trial point in one kernel (narrow rows only)
 bool trial_fusable(int prec, int R);
 void op_trial_fused(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);
-void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d);
+void op_proj(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int64_t rows);
 void op_copy_scale(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src, int dst);
 void op_gram(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int src);
 void op_pack_f64(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, const double *src, int r,
