@@ -1542,8 +1542,27 @@ static Task solve_main(Ctx c) {
       fprintf(stderr, "[hallar] t=%d beta=%.3g rank=%d pval=%.10g dval=%.10g pinf=%.2e gap=%.2e dinf=%.2e rounds=%lld\n",
               t, beta, r, pval, dval, pinf, gapr, dinf, (long long)res.n_rounds);
     if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
-      res.status = HALLAR_OK;
-      break;
+      // Certification: the Ritz value bounds lambda_min from above, and near
+      // the optimum a warm-started run can settle on a member of the cluster
+      // of smallest eigenvalues (one per primal column) above the minimum.
+      // A cold-started run of bounded length sees the whole cluster; its
+      // Ritz value, if smaller, only tightens theta and the dual value.
+      EigOut ec;
+      co_await lanczos(c, o.eig_frac * eps_t / tau2, std::min(o.eig_max_iter, 400), 0, ec);
+      if (ec.lam < lmin) {
+        lmin = ec.lam;
+        eres = ec.res;
+        theta = std::max(-lmin, 0.0);
+        dval = -bp - tau2 * theta;
+        gapr = std::fabs(pval - dval) / (1.0 + std::fabs(pval) + std::fabs(dval));
+        dinf = std::max(0.0, -((lmin - eres) + theta)) / (1.0 + hp.c_l1);
+        if (o.verbose)
+          fprintf(stderr, "[hallar] t=%d certification: lambda %.10g (cold) -> gap=%.2e dinf=%.2e\n", t, lmin, gapr, dinf);
+      }
+      if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
+        res.status = HALLAR_OK;
+        break;
+      }
     }
     if (now_s() - t0 > o.time_limit) {
       res.status = HALLAR_E_TIME_LIMIT;

@@ -16,11 +16,11 @@ times (FP32-mixed, default tile schedule):
 The solver's gap, like the paper's criterion, uses the eigensolver's
 smallest Ritz value, an upper bound on lambda_min.  Near the optimum of this
 SDP the smallest eigenvalues of C + A*(p) form a cluster (one per column of
-the rank-3 primal solution), and the warm-started Lanczos run can settle on a
-cluster member above the minimum: here theta is 0.006239 against eigsh's
-0.006255, so the exact gap is 1.22e-5 while the reported one is 3.95e-6.
-The test pins the Ritz bound (theta never above the exact value) and the
-exact gap within 2e-5.
+the rank-3 primal solution), and a warm-started Lanczos run can settle on a
+cluster member above the minimum (theta 0.006239 against eigsh's 0.006255,
+exact gap 1.22e-5 where 3.95e-6 was reported).  The solver therefore
+confirms convergence with a cold-started run; the test pins the Ritz bound
+(theta never above the exact value) and the exact gap within eps.
 """
 import functools
 
@@ -102,4 +102,5 @@ def test_fullsize_mc_solve_certificate():
     dval = float(-prob.b @ p - prob.tau2 * theta)
     assert abs(float(-prob.b @ p - prob.tau2 * res["theta"]) - res["dval"]) <= 1e-9 * (1.0 + abs(dval))
     gap = abs(pval - dval) / (1.0 + abs(pval) + abs(dval))
-    assert gap <= 2e-5, (gap, pval, dval, theta, res["theta"])
+    print(f"[fullsize] theta {res['theta']:.10g} exact {theta:.10g}; gap {res['gap']:.3e} exact {gap:.3e}", flush=True)
+    assert gap <= 1e-5 * (1.0 + 1e-6), (gap, pval, dval, theta, res["theta"])
