@@ -128,7 +128,9 @@ typedef struct {
   int32_t outer_iters;
   int32_t pad_;
   double pval, dval;     /* C . U U^T and -b^T p - tau^2 theta */
-  double theta;          /* max(-lambda_min(C + A*(p)), 0) */
+  double theta;          /* max(-lambda, 0), lambda the smallest Ritz value of
+                            C + A*(p) (an upper bound on lambda_min); at
+                            convergence also confirmed by a cold-started run */
   double pinf, gap, dinf;/* relative errors of eq. termination2 */
   double beta;           /* final penalty */
   double seconds;        /* wall-clock of the solve */
