@@ -212,3 +212,41 @@ def test_rank_cap_is_reported():
     res = oracle.hallar(prob, si.gaussian_u0(80, 3), oracle.Options(eps=1e-5, rank_cap=2))
     assert res.rank <= 2
     assert res.counters["truncations"] > 0
+
+
+@pytest.mark.parametrize("k1,k2,seed", [(8, 9, 1), (10, 10, 3)])
+def test_certified_lambda_min_on_clustered_spectrum(k1, k2, seed):
+    """+-1 tori have a cluster of smallest eigenvalues of C + A*(p) at the
+    optimum (one per primal column).  The returned theta is a Ritz bound
+    (theta <= max(-lambda_min, 0)) that must agree with LAPACK's lambda_min,
+    and the relative gap recomputed with the exact lambda_min must meet eps
+    (eq. termination2 with the exact dual value)."""
+    prob = si.maxcut_torus(k1, k2, seed=seed)
+    eps = 1e-5
+    res = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=eps))
+    assert res.status == "ok"
+    M = oracle.adjoint_apply(prob, np.concatenate([[1.0], res.p]), np.eye(prob.n))
+    w = np.linalg.eigvalsh(M)
+    assert w[2] - w[0] < 1e-4 * abs(w[0])           # the cluster the certification is for
+    th = max(-w[0], 0.0)
+    assert res.theta <= th + 1e-10
+    assert th - res.theta <= 1e-6 * (1 + th)
+    dval = -prob.b @ res.p - prob.tau2 * th
+    assert abs(res.pval - dval) / (1 + abs(res.pval) + abs(dval)) <= eps
+
+
+def test_objective_accuracy_bound():
+    """With the objective test on, a converged solve also has
+    |pval - dval| + |p^T r| <= eps (1 + |pval|) (the a-posteriori bound on
+    the objective error); MC exact recovery (Section 5.2) then puts pval
+    within eps of ||M||_* ."""
+    prob = si.mc_planted(40, 50, 2, 1400, seed=8)
+    A, B = prob.meta["A"], prob.meta["B"]
+    nuc = np.linalg.svd(A @ B.T, compute_uv=False).sum()
+    eps = 1e-5
+    res = oracle.hallar(prob, si.gaussian_u0(prob.n, 3), oracle.Options(eps=eps))
+    assert res.status == "ok"
+    r = oracle.a_tilde(prob, res.U)[1:] - prob.b
+    bound = abs(res.pval - res.dval) + abs(float(res.p @ r))
+    assert bound <= eps * (1 + abs(res.pval))
+    assert abs(res.pval - nuc) <= eps * (1 + nuc)
