@@ -12,10 +12,14 @@ Follows the cuHALLaR paper (arXiv 2505.13719) step by step:
 Readings where the paper is silent (the GPU solver uses the same numbers,
 defined on its own side):
   * beta_1 = 1; after outer iteration t (the paper only says "adaptive,
-    LANCELOT-like", Section 2): beta <- min(4 beta, 1e8) when
+    LANCELOT-like", Section 2): beta <- min(4 beta, beta_max) when
     ||A(X_t) - b|| > 0.5 ||A(X_{t-1}) - b|| and the relative infeasibility is
-    at least 0.1 times the larger of the relative gap and dual infeasibility;
-    otherwise beta is kept.
+    at least 0.1 times the larger of the relative gap and dual infeasibility,
+    16 beta when ||A(X_t) - b|| > 0.9 ||A(X_{t-1}) - b||; otherwise beta is
+    kept.  beta_max = 1e16 only guards against overflow: the penalty an
+    instance needs scales with its data (the Lovasz theta SDP of an n-vertex
+    graph of degree d needs multipliers of order n/d on residuals of order
+    1/n, so beta near n^2: about 1.7e7 for the 12-cube, 1e12 for the 20-cube).
   * eps_t = max(eps1 * 0.5^(t-1), eps_floor) * (1 + max(|pval_{t-1}|, |g_t(U_{t-1})|))
     with eps1 = 1e-2, eps_floor = 0.2 * eps (pval_0 = C . U_0 U_0^T; the AL
     value at the start of the outer iteration keeps the scale right when the
@@ -78,7 +82,7 @@ class Options:
     eps: float = 1e-5
     beta1: float = 1.0
     beta_growth: float = 4.0
-    beta_max: float = 1e8
+    beta_max: float = 1e16
     beta_rule: str = "ratio"
     infeas_ratio: float = 0.5
     pinf_gate: float = 0.1

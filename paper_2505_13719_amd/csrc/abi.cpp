@@ -70,7 +70,7 @@ void hallar_default_options(hallar_options *o) {
   o->eps = 1e-5;
   o->beta1 = 1.0;
   o->beta_growth = 4.0;
-  o->beta_max = 1e8;
+  o->beta_max = 1e16;
   o->infeas_ratio = 0.5;
   o->pinf_gate = 0.1;
   o->stall_ratio = 0.9;

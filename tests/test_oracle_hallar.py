@@ -250,3 +250,17 @@ def test_objective_accuracy_bound():
     bound = abs(res.pval - res.dval) + abs(float(res.p @ r))
     assert bound <= eps * (1 + abs(res.pval))
     assert abs(res.pval - nuc) <= eps * (1 + nuc)
+
+
+@pytest.mark.parametrize("d", [8, 10])
+def test_theta_hamming_closed_form(d):
+    """Lovasz theta of the Hamming graph H(d, 2) (the d-cube, Section 5.3,
+    Table tab:reduced_hamming_graphs): bipartite, hence perfect, so
+    theta = alpha = n/2.  The penalty has to climb to about n^2 before the
+    edge constraints bind."""
+    n = 1 << d
+    prob = si.theta_problem(n, *si.hypercube_edges(d))
+    res = oracle.hallar(prob, si.gaussian_u0(n, 5), oracle.Options(eps=1e-5))
+    assert res.status == "ok"
+    assert abs(res.pval + n / 2) <= 1e-5 * (1 + n / 2)
+    assert max(res.pinf, res.gap, res.dinf) <= 1e-5
