@@ -40,8 +40,11 @@ defined on its own side):
   * After every nonconvex solve, Y is rotated onto the eigenvectors of
     Y^T Y and directions with sigma^2 <= 1e-14 sigma_max^2 are dropped (Y Y^T
     unchanged up to that size).  Rank cap: when the Frank-Wolfe iterate has
-    more columns than the cap, only its cap largest directions are kept; each
-    such truncation is counted and reported.
+    more columns than the cap, its numerically null directions are dropped;
+    if it still has too many, the solve stops with status "rank_cap" and
+    returns the iterate before the step (the cap is never met silently).
+    With rank_cap_truncate only the cap largest directions are kept instead,
+    and each such truncation is counted.
   * Eigen solve: Lanczos stops once the Ritz residual is
     <= eig_frac * eps_t / tau^2 (floor 1e-13 max(1, |lambda|)), so that the
     error it puts into the gap G.YY^T + tau^2 theta stays below eig_frac eps_t.
@@ -108,6 +111,7 @@ class Options:
     cert_max_iter: int = 400        # matvecs of the cold-started certification run (0: none)
     obj_check: bool = True          # also stop only when |pval - dval| + |p^T r| <= eps (1 + |pval|)
     rank_cap: int = 0               # 0: unbounded
+    rank_cap_truncate: bool = False  # at the cap: keep the largest directions (else stop, status "rank_cap")
     drop_tol: float = 1e-14
     time_limit: float = 3600.0
     seed: int = 0                   # eigen start vectors
@@ -359,8 +363,17 @@ def hallar(prob, U0, opts: Options = None, p0=None):
             alpha = fw_alpha(gap_fw, TY[1:], a_tilde(prob, y.reshape(n, 1))[1:], prob.tau2, beta)
             Yt = fw_step(Y, y, theta, alpha, tau)
             if opts.rank_cap and Yt.shape[1] > opts.rank_cap:
-                counters["truncations"] += 1
-                Yt = _compress(Yt, opts.drop_tol, opts.rank_cap)
+                # rank cap: drop numerically null directions; if the step still
+                # needs more columns, stop ("rank_cap", the iterate before the
+                # step is returned) unless truncation was asked for
+                if opts.rank_cap_truncate:
+                    counters["truncations"] += 1
+                    Yt = _compress(Yt, opts.drop_tol, opts.rank_cap)
+                else:
+                    Yt = _compress(Yt, opts.drop_tol)
+                    if Yt.shape[1] > opts.rank_cap:
+                        status = "rank_cap"
+                        break
             gY, _, _ = g.eval(Yt)
         else:
             status = "iter_limit"

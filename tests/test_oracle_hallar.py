@@ -204,12 +204,29 @@ def test_aipp_invariants():
         assert np.linalg.norm(N - c * W) <= 1e-8 * (1 + np.linalg.norm(N))
 
 
-def test_rank_cap_is_reported():
-    """A rank cap below what Frank-Wolfe asks for is counted, never silent."""
+def _capped_instance():
     rng = np.random.default_rng(0)
     i, j = si.er_edges(80, 0.1, rng)
-    prob = si.maxcut_problem(80, i, j, si.pm1_weights(i.size, rng))
+    return si.maxcut_problem(80, i, j, si.pm1_weights(i.size, rng))
+
+
+def test_rank_cap_stops_with_status():
+    """A rank cap below what Frank-Wolfe asks for stops the solve with status
+    "rank_cap" and the iterate before the step (rank <= cap), never silently."""
+    prob = _capped_instance()
     res = oracle.hallar(prob, si.gaussian_u0(80, 3), oracle.Options(eps=1e-5, rank_cap=2))
+    assert res.status == "rank_cap"
+    assert res.rank <= 2
+    assert res.counters["truncations"] == 0
+    assert np.linalg.norm(res.U) <= math.sqrt(prob.tau2) * (1 + 1e-12)
+
+
+def test_rank_cap_truncation_is_counted():
+    """With truncation asked for, the cap's largest directions are kept and
+    every truncation is counted."""
+    prob = _capped_instance()
+    res = oracle.hallar(prob, si.gaussian_u0(80, 3),
+                        oracle.Options(eps=1e-5, rank_cap=2, rank_cap_truncate=True, outer_max_iter=6))
     assert res.rank <= 2
     assert res.counters["truncations"] > 0
 
