@@ -49,7 +49,7 @@ typedef enum {
   HALLAR_E_NOT_CONVERGED = 5,  /* eigen solve stopped above its tolerance */
   HALLAR_E_ITER_LIMIT = 6,     /* an iteration cap of the solver was reached */
   HALLAR_E_TIME_LIMIT = 7,     /* the solve's wall-clock limit was reached */
-  HALLAR_E_RANK_CAP = 8,       /* reserved: rank cap could not be honoured */
+  HALLAR_E_RANK_CAP = 8,       /* a Frank-Wolfe step needs more columns than opts.rank_cap */
   HALLAR_E_NUMERICAL = 9,      /* NaN/Inf, or the prox stepsize underflowed */
   HALLAR_E_BUSY = 10           /* pool: no free slot right now */
 } hallar_status;
@@ -95,7 +95,11 @@ typedef struct {
   double eig_tol, eig_frac;         /* Lanczos: residual <= max(eig_frac eps_t / tau^2, eig_tol max(1,|lambda|)) */
   int32_t eig_kmax;                 /* Lanczos basis size before a thick restart (<= 64) */
   int32_t eig_max_iter;             /* Lanczos matvec cap per eigen solve */
-  int32_t rank_cap;                 /* columns of U after a step; 0 = none (then at most 63) */
+  int32_t rank_cap;                 /* columns of U after a Frank-Wolfe step; 0 = none (then at most 63).
+                                       A step that would exceed it first drops the directions with
+                                       sigma^2 <= drop_tol sigma_max^2; if that is not enough the solve
+                                       stops with HALLAR_E_RANK_CAP and returns the iterate before the
+                                       step, unless rank_cap_truncate is set */
   double drop_tol;                  /* drop directions with sigma^2 <= drop_tol sigma_max^2 */
   double time_limit;                /* seconds per solve */
   uint64_t seed;                    /* Lanczos start vectors and default U0 */
@@ -116,7 +120,13 @@ typedef struct {
                                        kernels; 0 (default): one kernel where the instance recomputes its
                                        lower half, has no low-rank objective term and narrow rows
                                        (r <= 8 in FP32-mixed, r <= 4 in FP64).  Both give identical bits. */
-  int32_t pad_;
+  int32_t obj_check;                /* 1 (default): besides the three relative errors of eq. termination2
+                                       the solve stops only when |pval - dval| + |p^T (A(X) - b)| <=
+                                       eps (1 + |pval|), an a-posteriori bound on the objective error (the
+                                       relative gap divides by about twice the objective); 0: off */
+  int32_t rank_cap_truncate;        /* 1: at the rank cap keep the cap's largest directions of Y Y^T and
+                                       count each such truncation in n_truncations (X changes); 0
+                                       (default): stop with HALLAR_E_RANK_CAP */
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);
@@ -129,13 +139,16 @@ typedef struct {
   int32_t pad_;
   double pval, dval;     /* C . U U^T and -b^T p - tau^2 theta */
   double theta;          /* max(-lambda, 0), lambda the smallest Ritz value of
-                            C + A*(p) (an upper bound on lambda_min); at
-                            convergence also confirmed by a cold-started run */
+                            C + A*(p) (an upper bound on lambda_min); once the
+                            relative errors pass, rechecked by a cold-started
+                            run whose Ritz value is taken if smaller */
   double pinf, gap, dinf;/* relative errors of eq. termination2 */
   double beta;           /* final penalty */
   double seconds;        /* wall-clock of the solve */
   int64_t n_sddmm, n_spmm, n_matvec, n_fista_trials, n_aipp_iters;
   int64_t n_hlr_iters, n_eig_calls, n_truncations, n_rounds;
+  double obj_bound;      /* |pval - dval| + |p^T (A(X) - b)| at the last outer iteration: an
+                            a-posteriori estimate of |pval - P*| (see opts.obj_check) */
 } hallar_result;
 
 typedef struct {

@@ -1504,18 +1504,32 @@ static Task solve_main(Ctx c) {
       S.prm.buf[1] = Ynew;
       S.prm.r = r;
       co_await OpAwait{S};
-      c.release(Y);
-      Y = -1;
+      const int r_prev = r, R_prev = S.cur_R;
       U = Ynew;
       r = rnew;
       S.cur_R = RD;
       // at most R_MAX - 1 columns survive a step, so the next one fits R_MAX
       const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, R_MAX - 1) : R_MAX - 1;
       if (r > cap) {
+        // rank cap: drop the numerically null directions first; if the step
+        // still needs more columns than the cap, stop with E_RANK_CAP and
+        // return the iterate before the step (or, on request, keep the cap's
+        // largest directions and count the truncation)
         bool tr = false;
-        co_await compress(c, U, r, cap, tr);
+        co_await compress(c, U, r, o.rank_cap_truncate ? cap : 0, tr);
         if (tr) res.n_truncations++;
+        if (r > cap) {
+          c.release(U);
+          U = Y;
+          Y = -1;
+          r = r_prev;
+          S.cur_R = R_prev;
+          res.status = HALLAR_E_RANK_CAP;
+          break;
+        }
       }
+      c.release(Y);
+      Y = -1;
       eval(U, 0, 0);
       co_await OpAwait{S};
       gY = c.res(S_G_EVAL);
@@ -1529,7 +1543,7 @@ static Task solve_main(Ctx c) {
     // p_t = p + beta (A(U U^T) - b) (eq. dual update SDP Algo 2)
     c.op(OP_SETP);
     co_await OpAwait{S};
-    const double bp = c.res(S_BP), rr = c.res(S_RR);
+    const double bp = c.res(S_BP), rr = c.res(S_RR), ptr = c.res(S_PTR);
     pval = TYT0;
     dval = -bp - tau2 * theta;
     const double rnorm = std::sqrt(std::max(rr, 0.0));
@@ -1541,6 +1555,15 @@ static Task solve_main(Ctx c) {
     if (o.verbose)
       fprintf(stderr, "[hallar] t=%d beta=%.3g rank=%d pval=%.10g dval=%.10g pinf=%.2e gap=%.2e dinf=%.2e rounds=%lld\n",
               t, beta, r, pval, dval, pinf, gapr, dinf, (long long)res.n_rounds);
+    // objective accuracy: the relative gap of eq. termination2 divides by
+    // about twice the objective, so it alone admits an objective error near
+    // 2 eps; weak duality puts P* above dval, pval above dval - |p^T r|, and
+    // P* <= pval + p*^T r for an optimal multiplier p*, so with p_t near p*
+    // |pval - dval| + |p_t^T r| bounds |pval - P*|
+    auto obj_ok = [&]() {
+      res.obj_bound = std::fabs(pval - dval) + std::fabs(ptr);
+      return !o.obj_check || res.obj_bound <= o.eps * (1.0 + std::fabs(pval));
+    };
     if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
       // Certification: the Ritz value bounds lambda_min from above, and near
       // the optimum a warm-started run can settle on a member of the cluster
@@ -1559,11 +1582,12 @@ static Task solve_main(Ctx c) {
         if (o.verbose)
           fprintf(stderr, "[hallar] t=%d certification: lambda %.10g (cold) -> gap=%.2e dinf=%.2e\n", t, lmin, gapr, dinf);
       }
-      if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
+      if (std::max(pinf, std::max(gapr, dinf)) <= o.eps && obj_ok()) {
         res.status = HALLAR_OK;
         break;
       }
     }
+    obj_ok();
     if (now_s() - t0 > o.time_limit) {
       res.status = HALLAR_E_TIME_LIMIT;
       break;

@@ -95,6 +95,7 @@ enum ResSlot : int {
   S_GR2T,               // ||GR||^2 of a FISTA trial (rounding bound of <GR, d>)
   S_GR2A,               // ||GR||^2 at ADAP-FISTA's output (rounding bound of R_j)
   S_LZ_W2,              // ||G v_j||^2 before reorthogonalisation (second-pass test)
+  S_PTR,                // p_t^T (A(X_t) - b) after the dual update (objective accuracy test)
   S_COUNT
 };
 

@@ -1308,19 +1308,21 @@ __global__ __launch_bounds__(BLOCK) void k_fw_den_gen(const int32_t *__restrict_
   if (blockIdx.x * BLOCK < I.m) block_partials<1>(acc, I, I.ntiles + blockIdx.x);
 }
 
-// p <- y'(Y) and partial b^T p (dual value), ||T(Y) - b||^2.
+// p <- y'(Y) and partial b^T p (dual value), ||T(Y) - b||^2 and p^T (T(Y) - b)
+// with the new p (the objective accuracy estimate |pval - dval| + |p^T r|).
 __global__ __launch_bounds__(BLOCK) void k_set_p(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts) {
   const InstDev &I = insts[ilist[blockIdx.y]];
   const int l = blockIdx.x * BLOCK + threadIdx.x;
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   if (l < I.m) {
     const double y = I.yp[l];
     I.p[l] = y;
     acc[0] = I.b[l] * y;
     const double r = I.TY[l] - I.b[l];
     acc[1] = r * r;
+    acc[2] = y * r;
   }
-  if (blockIdx.x * BLOCK < I.m) block_partials<2>(acc, I, I.ntiles + blockIdx.x);
+  if (blockIdx.x * BLOCK < I.m) block_partials<3>(acc, I, I.ntiles + blockIdx.x);
 }
 
 // {p_l, b_l} per pair in pair order (direct mode, zeros for unconstrained
@@ -1900,10 +1902,11 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(const int32_t *__restrict__ i
     }
     case RD_SETP: {
       const int ex = (I.m + BLOCK - 1) / BLOCK;
-      if (ex > 0) reduce_slots(I, 0, 2, nt, ex, E);
+      if (ex > 0) reduce_slots(I, 0, 3, nt, ex, E);
       if (tid == 0) {
         res[S_BP] = ex > 0 ? E[0] : 0.0;
         res[S_RR] = ex > 0 ? E[1] : 0.0;
+        res[S_PTR] = ex > 0 ? E[2] : 0.0;
       }
       break;
     }

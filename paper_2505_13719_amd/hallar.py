@@ -42,7 +42,8 @@ class hallar_options(C.Structure):
                 ("eig_frac", C.c_double), ("eig_kmax", C.c_int32), ("eig_max_iter", C.c_int32),
                 ("rank_cap", C.c_int32), ("drop_tol", C.c_double), ("time_limit", C.c_double),
                 ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32), ("autotune", C.c_int32),
-                ("lower_gather", C.c_int32), ("unfused_trial", C.c_int32), ("pad_", C.c_int32)]
+                ("lower_gather", C.c_int32), ("unfused_trial", C.c_int32), ("obj_check", C.c_int32),
+                ("rank_cap_truncate", C.c_int32)]
 
 
 class hallar_result(C.Structure):
@@ -51,7 +52,8 @@ class hallar_result(C.Structure):
                 ("gap", C.c_double), ("dinf", C.c_double), ("beta", C.c_double), ("seconds", C.c_double),
                 ("n_sddmm", C.c_int64), ("n_spmm", C.c_int64), ("n_matvec", C.c_int64),
                 ("n_fista_trials", C.c_int64), ("n_aipp_iters", C.c_int64), ("n_hlr_iters", C.c_int64),
-                ("n_eig_calls", C.c_int64), ("n_truncations", C.c_int64), ("n_rounds", C.c_int64)]
+                ("n_eig_calls", C.c_int64), ("n_truncations", C.c_int64), ("n_rounds", C.c_int64),
+                ("obj_bound", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
