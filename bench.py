@@ -5,8 +5,10 @@ gap on one GPU, with the dominant kernel's achieved HBM bandwidth.
 One step is one complete HALLaR solve (operators, ADAP-FISTA/ADAP-AIPP,
 Lanczos, Frank-Wolfe, multiplier updates, relative termination) of a seeded
 synthetic instance resident in HBM.  Workloads (--workload):
-  mc      matrix completion, 1e5 x 1e5 rank 3, m = 1.2e7, FP32-mixed,
-          rank cap 16 (default)
+  mc      matrix completion, 1e5 x 1e5 rank 3, m = 1.2e7, FP64 (the
+          paper's precision), rank cap 16 (default); then the same instance
+          in FP32-mixed (--mixed-steps), reported beside it with its error
+          against the FP64 solve
   torus   MaxCut SDP, 1000 x 1000 torus (n = 1e6), +-1 weights, FP32-mixed,
           rank cap 32 (does not reach 1e-5 within the limits: its solution
           rank grows with n far beyond 32)
@@ -35,17 +37,17 @@ def workload(name):
     import sdp_instances as si
     from paper_2505_13719_amd import hallar as H
     if name == "torus":
-        return si.maxcut_torus(1000, 1000, seed=2), H.FP32_MIXED, dict(rank_cap=32), \
+        return si.maxcut_torus(1000, 1000, seed=2), H.FP32_MIXED, dict(rank_cap=32, rank_cap_truncate=1), \
             {"workload": "maxcut_torus_1000x1000_pm1", "n": 10 ** 6, "edges": 2 * 10 ** 6, "rank_cap": 32}
     if name == "er800":
-        return si.maxcut_er_800(1), H.FP64, dict(rank_cap=16), \
+        return si.maxcut_er_800(1), H.FP64, dict(rank_cap=16, rank_cap_truncate=1), \
             {"workload": "maxcut_er_800_p0.02", "n": 800, "rank_cap": 16}
     if name == "theta":
         return si.theta_er(50_000, 10.0, seed=3), H.FP32_MIXED, dict(rank_cap=64), \
             {"workload": "theta_er_50000_deg10", "n": 50_000, "rank_cap": 64}
     if name == "mc":
         n1 = n2 = 100_000
-        return si.mc_planted(n1, n2, 3, 20 * 3 * (n1 + n2), seed=4), H.FP32_MIXED, dict(rank_cap=16), \
+        return si.mc_planted(n1, n2, 3, 20 * 3 * (n1 + n2), seed=4), H.FP64, dict(rank_cap=16), \
             {"workload": "matrix_completion_1e5x1e5_r3_m1.2e7", "n": n1 + n2, "m": 20 * 3 * (n1 + n2)}
     raise ValueError(name)
 
@@ -55,10 +57,11 @@ PROFILE_TAG = {"mc": "mc_1e5x1e5_r3", "torus": "torus_1000x1000_pm1", "er800": "
 CLASS_KERNEL = {"sddmm": "k_sddmm<", "spmm": "k_spmm<", "lanczos_spmv": "k_lz_spmv", "sddmm_spmm": "k_trial_fused<"}
 
 
-def counted_traffic(workload_name, cls):
+def counted_traffic(workload_name, cls, prec=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (two rocprofv3 --pmc passes, calibrated on a 1 GiB copy), or None
-    when there is none or the kernels changed since it was taken."""
+    when there is none or the kernels changed since it was taken.  prec
+    (0 FP64, 1 FP32-mixed) selects the kernel's instantiation."""
     import hashlib
     tag = PROFILE_TAG.get(workload_name)
     if tag is None or cls not in CLASS_KERNEL:
@@ -72,7 +75,8 @@ def counted_traffic(workload_name, cls):
     if "kernels.hip sha256[:16] = " + sha not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch[") and CLASS_KERNEL[cls] in line:
+        pat = CLASS_KERNEL[cls] + ("" if prec is None else ("double" if prec == 0 else "float"))
+        if line.startswith("traffic_bytes_per_launch[") and pat in line:
             return float(line.split("=")[-1])
     return None
 
@@ -95,48 +99,78 @@ def roofline_from_profile(prof):
                 us_per_launch=1e3 * v["ms"] / max(v["launches"], 1)), table
 
 
-def cpu_baseline(prob, res, budget_s=20.0):
-    """Oracle timed on a bounded sample: FISTA-trial-equivalent evaluations
-    (2 A~(UU^T) + 1 adjoint) and Lanczos products on the same instance at the
-    GPU solve's final rank, scaled by the GPU solve's operation counts."""
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
+def cpu_baseline(prob, res, budget_s=20.0, c0_solve=False):
+    """The FP64 oracle timed on the host on a bounded sample of the same
+    instance: its SDDMM (A~(UU^T)), SpMM ((C + A*(y))U) and Lanczos product
+    (with full reorthogonalisation) at the GPU solve's final rank, each timed
+    on its own, then scaled by the GPU solve's operation counts (a FISTA trial
+    is 2 SDDMM + 1 SpMM).  `cores` is the average number of threads the
+    sample kept busy (process CPU time / wall time).  With c0_solve, also one
+    complete oracle solve of the 800-vertex MaxCut SDP (eps = 1e-5; about
+    two minutes on the host, so not in the default run)."""
     import numpy as np
 
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = 1
+    import sdp_instances as si
+    model, nproc = host_cpu()
     r = max(int(res["rank"]), 1)
     rng = np.random.default_rng(0)
     U = rng.standard_normal((prob.n, r)) / math.sqrt(prob.n * r) * math.sqrt(prob.tau2)
-    counters = dict(sddmm=0, spmm=0)
-    g = oracle.ALFunction(prob, np.zeros(prob.m), 1.0, counters)
-    t0 = time.perf_counter()
-    trials = 0
-    while True:
-        gv, T, y = g.eval(U)
-        G = g.grad_from(U, y)
-        g.eval(U - 1e-3 * G)
-        trials += 1
-        if time.perf_counter() - t0 > budget_s / 2 or trials >= 50:
-            break
-    t_trial = (time.perf_counter() - t0) / trials
-    ptil = np.concatenate([[1.0], np.zeros(prob.m)])
+    ptil = np.concatenate([[1.0], rng.standard_normal(prob.m) * 1e-3])
+    cpu0, wall0 = time.process_time(), time.perf_counter()
+
+    def timed(fn, share):
+        t0, k = time.perf_counter(), 0
+        while True:
+            fn()
+            k += 1
+            if time.perf_counter() - t0 > share or k >= 20:
+                return (time.perf_counter() - t0) / k, k
+
+    t_sddmm, k1 = timed(lambda: oracle.a_tilde(prob, U), budget_s / 3)
+    t_spmm, k2 = timed(lambda: oracle.adjoint_apply(prob, ptil, U), budget_s / 3)
     M = oracle.adjoint_sparse(prob, ptil)
     t1 = time.perf_counter()
     kmax = 32 if prob.n > 100_000 else 64
-    lam, v, info = oracle.min_eig(lambda x: M @ x, prob.n, rng.standard_normal(prob.n), tol=1e-30, kmax=kmax,
-                                  max_restarts=1)
+    _, _, info = oracle.min_eig(lambda x: M @ x, prob.n, rng.standard_normal(prob.n), tol=1e-30, kmax=kmax,
+                                max_restarts=1)
     t_mv = (time.perf_counter() - t1) / max(info["iters"], 1)
+    cores = (time.process_time() - cpu0) / max(time.perf_counter() - wall0, 1e-9)
+    t_trial = 2 * t_sddmm + t_spmm
     est = res["n_fista_trials"] * t_trial + res["n_matvec"] * t_mv
-    return dict(value=round(1.0 / est, 8), unit="solves/s", cores=int(cores), kind="oracle",
-                sample=f"{trials} FISTA-trial evaluations (2 SDDMM + 1 SpMM, rank {r}) and {info['iters']} "
-                       f"Lanczos products with full reorthogonalisation on the full instance, "
-                       f"{t_trial:.3f} s/trial and {t_mv * 1e3:.1f} ms/product, scaled by the GPU solve's "
-                       f"{res['n_fista_trials']} trials and {res['n_matvec']} products "
-                       f"(estimated oracle solve {est:.0f} s)",
-                est_seconds=round(est, 1))
+    out = dict(value=round(1.0 / est, 8), unit="solves/s", cores=round(cores, 1), kind="oracle",
+               sample=f"{k1} SDDMM and {k2} SpMM calls (rank {r}) and {info['iters']} Lanczos products with full "
+                      f"reorthogonalisation on the full instance; a FISTA trial (2 SDDMM + 1 SpMM) costs "
+                      f"{t_trial:.3f} s, scaled by the GPU solve's {res['n_fista_trials']} trials and "
+                      f"{res['n_matvec']} products (estimated oracle solve {est:.0f} s)",
+               per_op_ms={"sddmm": round(1e3 * t_sddmm, 1), "spmm": round(1e3 * t_spmm, 1),
+                          "lanczos_product": round(1e3 * t_mv, 2)},
+               est_seconds=round(est, 1), cpu_model=model, nproc=nproc)
+    if c0_solve:
+        c0 = si.maxcut_er_800(1)
+        t2 = time.perf_counter()
+        rc0 = oracle.hallar(c0, si.gaussian_u0(c0.n, 7),
+                            oracle.Options(eps=1e-5, rank_cap=16, rank_cap_truncate=True, time_limit=120.0))
+        out["maxcut_er800_oracle_solve"] = {"seconds": round(time.perf_counter() - t2, 2), "status": rc0.status,
+                                            "pval": rc0.pval, "solves_per_s": round(1.0 / (time.perf_counter() - t2), 4)}
+    return out
 
 
 def copy_peak_gbs(reps=5):
@@ -157,16 +191,15 @@ def copy_peak_gbs(reps=5):
     return round(2 * (1 << 30) / sec / 1e9, 1)
 
 
-def bench_solve(args):
-    import numpy as np  # noqa: F401
+def timed_solves(prob, prec, kw, steps, warmup, args, label):
+    """Create a handle, run `warmup` untimed and `steps` timed solves from the
+    same U0 (instance and U0 resident in HBM), return the wall time of the
+    timed ones, the last result, the per-class profile and the schedule."""
     import torch
 
     import sdp_instances as si
     from paper_2505_13719_amd import hallar as H
 
-    prob, prec, kw, cfg = workload(args.workload)
-    if args.precision:
-        prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
     dev = torch.device("cuda:0")
     opts = H.options(eps=1e-5, profile=args.profile, time_limit=3000.0, verbose=args.verbose, autotune=args.autotune,
                      **kw)
@@ -176,26 +209,50 @@ def bench_solve(args):
     schedule = dict(zip(("min_rows", "ent_cap", "ntiles"), H.hallar_schedule(h)))
     U0 = torch.tensor(si.gaussian_u0(prob.n, 7), device=dev)
     res = None
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         res = H.hallar_solve(h, U0)
-        print(f"[bench] warmup solve: {res['status']} {res['seconds']:.2f}s", file=sys.stderr, flush=True)
+        print(f"[bench] {label} warmup solve: {res['status']} {res['seconds']:.2f}s", file=sys.stderr, flush=True)
     H.hallar_profile(h, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         res = H.hallar_solve(h, U0)
-        print(f"[bench] step {k}: {res['status']} pval={res['pval']:.9g} gap={res['gap']:.2e} "
+        print(f"[bench] {label} step {k}: {res['status']} pval={res['pval']:.9g} gap={res['gap']:.2e} "
               f"rank={res['rank']} {res['seconds']:.2f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = H.hallar_profile(h)
     H.hallar_destroy(h)
+    return dt, res, prof, schedule, t_build
+
+
+def closed_form_optimum(prob):
+    """The SDP's optimum where a closed form is known: noise-free matrix
+    completion with exact recovery (||A B^T||_* from QR factors and an r x r
+    SVD).  None otherwise."""
+    import numpy as np
+    if "A" not in prob.meta:
+        return None
+    _, ra = np.linalg.qr(prob.meta["A"])
+    _, rb = np.linalg.qr(prob.meta["B"])
+    return float(np.linalg.svd(ra @ rb.T, compute_uv=False).sum())
+
+
+def bench_solve(args):
+    from paper_2505_13719_amd import hallar as H
+
+    prob, prec, kw, cfg = workload(args.workload)
+    if args.precision:
+        prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
+    dt, res, prof, schedule, t_build = timed_solves(prob, prec, kw, args.steps, args.warmup, args,
+                                                    "fp64" if prec == H.FP64 else "fp32_mixed")
     roof, table = roofline_from_profile(prof)
     if roof:
-        roof["traffic"] = counted_traffic(args.workload, roof["kernel"])
+        roof["traffic"] = counted_traffic(args.workload, roof["kernel"], prec)
         # the same achieved rate against what a plain copy reaches here
         roof["copy_gbs"] = copy_peak_gbs()
         roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
+    opt = closed_form_optimum(prob)
     out = {
         "metric": "SDP solves/s at 1e-5 rel gap",
         "value": round(args.steps / dt, 6),
@@ -210,16 +267,33 @@ def bench_solve(args):
         "dtype": "f64" if prec == H.FP64 else "f32+f64",
         "data": "synthetic",
         "config": dict(cfg, precision="fp64" if prec == H.FP64 else "fp32_mixed", eps=1e-5),
-        "solve": {k: res[k] for k in ("status", "pval", "dval", "pinf", "gap", "dinf", "rank", "outer_iters",
-                                      "n_fista_trials", "n_matvec", "n_hlr_iters", "n_eig_calls", "n_rounds",
-                                      "n_truncations")},
+        "solve": {k: res[k] for k in ("status", "pval", "dval", "pinf", "gap", "dinf", "obj_bound", "rank",
+                                      "outer_iters", "n_fista_trials", "n_matvec", "n_hlr_iters", "n_eig_calls",
+                                      "n_rounds", "n_truncations")},
         "roofline": roof,
         "kernels": table,
         "create_s": round(t_build, 2),
         "schedule": dict(schedule, autotuned=bool(args.autotune)),
     }
+    if opt is not None:
+        out["solve"]["closed_form_optimum"] = opt
+        out["solve"]["objective_rel_error"] = abs(res["pval"] - opt) / (1.0 + abs(opt))
+    if prec == H.FP64 and args.mixed_steps > 0:
+        # the FP32-mixed systems form on the same instance, timed after the
+        # headline steps, with its error against the FP64 solve
+        dt32, r32, prof32, _, _ = timed_solves(prob, H.FP32_MIXED, kw, args.mixed_steps, 1, args, "fp32_mixed")
+        roof32, _ = roofline_from_profile(prof32)
+        v32 = args.mixed_steps / dt32
+        mixed = {"solves_per_s": round(v32, 6), "steps": args.mixed_steps,
+                 "speedup_vs_fp64": round(v32 / out["value"], 3), "status": r32["status"], "pval": r32["pval"],
+                 "gap": r32["gap"], "pinf": r32["pinf"], "obj_bound": r32["obj_bound"],
+                 "rel_diff_vs_fp64": abs(r32["pval"] - res["pval"]) / (1.0 + abs(res["pval"])),
+                 "dominant_kernel": roof32 and {k: roof32[k] for k in ("kernel", "achieved", "frac", "us_per_launch")}}
+        if opt is not None:
+            mixed["objective_rel_error"] = abs(r32["pval"] - opt) / (1.0 + abs(opt))
+        out["fp32_mixed"] = mixed
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, res, budget_s=args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(prob, res, budget_s=args.cpu_budget, c0_solve=args.cpu_c0_solve)
     return out
 
 
@@ -374,6 +448,10 @@ def main():
     ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
     ap.add_argument("--autotune", type=int, default=0, help="1: tune the tile schedule at create (timed outside the steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-c0-solve", action="store_true",
+                    help="cpu_baseline: also time one complete oracle solve of the 800-vertex MaxCut SDP")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="FP64 runs: also time this many FP32-mixed solves of the same instance (0: none)")
     ap.add_argument("--served-requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per second (0: all at t = 0)")
     ap.add_argument("--budget-gb", type=float, default=64.0)

@@ -184,12 +184,17 @@ hallar_status hallar_describe(hallar_t h, int64_t *pairs, int64_t *sym_nnz, int6
  * T[0] = C . UU^T, T[l] = A_l . UU^T for l = 1..m.
  * U: device, n x r row-major with leading dimension ldu >= r, of the
  * handle's operator type (double for FP64, float for FP32_MIXED);
- * 1 <= r <= 64.  T: device double[m + 1].  Asynchronous on `stream`. */
+ * 1 <= r <= 64.  T: device double[m + 1].  Asynchronous on `stream`.
+ * U is read in place when r is a column bucket of the handle (FP32: 4, 8,
+ * 16, 32, 64; FP64: 2, 4, 8, ...), ldu = r and U is 16-byte aligned;
+ * otherwise it is first copied into a zero-padded work buffer. */
 hallar_status hallar_eval_AUUt(hallar_t h, const void *U, int32_t r, int64_t ldu, double *T, void *stream);
 
 /* W = A~*(1, p) U = (C + sum_l p_l A_l) U (Section 4.2, eq. Adjoint
  * calculation; Algorithms 4 and 5).  p: device double[m].  U as above; W:
- * device n x r, leading dimension ldw >= r, operator type.  Asynchronous. */
+ * device n x r, leading dimension ldw >= r, operator type.  Asynchronous.
+ * With r a column bucket and ldu = ldw = r (16-byte aligned), U is read and
+ * W written in place (no packing copy), unless the two overlap. */
 hallar_status hallar_adjoint_spmm(hallar_t h, const double *p, const void *U, int32_t r, int64_t ldu,
                                   void *W, int64_t ldw, void *stream);
 
@@ -282,11 +287,12 @@ hallar_status hallar_pool_usage(hallar_pool_t pool, size_t *used, size_t *budget
 /* Kernel classes timed with HIP events recorded on the library's stream
  * around each launch: 0 SDDMM (A~(UU^T) + AL epilogue), 1 SpMM
  * ((C + A*(y))U + epilogue), 2 Lanczos SpMV, 3 Lanczos reorthogonalisation,
- * 4 vector updates, 5 reductions, 6 other.  For each class: total
+ * 4 vector updates, 5 reductions, 6 other, 7 the fused FISTA trial kernel
+ * (SDDMM and gradient SpMM in one row walk).  For each class: total
  * milliseconds, launches, and algorithmic bytes (every index, value and
  * constraint array read once, U read once, outputs written once).  Counters
  * accumulate since the handle/pool was created or last reset (reset != 0).
- * Arrays are host, length n_classes (<= 7). */
+ * Arrays are host, length n_classes (<= 8). */
 hallar_status hallar_profile(hallar_t h, double *ms, int64_t *launches, double *bytes, int32_t n_classes, int32_t reset);
 hallar_status hallar_pool_profile(hallar_pool_t pool, double *ms, int64_t *launches, double *bytes, int32_t n_classes,
                                   int32_t reset);

@@ -388,6 +388,9 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   std::vector<int32_t> il{s};
   put(base, L.ilist, il, st);
   if (h.m > 0) (void)hipMemsetAsync(base + L.p, 0, (size_t)h.m * 8, st);
+  // {p_l, b_l} copies start defined (the standalone SDDMM's epilogue reads them)
+  if (h.direct && h.npairs > 0) (void)hipMemsetAsync(base + L.upb, 0, (size_t)h.npairs * 16, st);
+  if (h.low_recompute && h.nlower > 0) (void)hipMemsetAsync(base + L.low_pb, 0, (size_t)h.nlower * 16, st);
   (void)hipMemsetAsync(base + L.Z0, 0, 2 * LR_MAX * R_MAX * 8, st);
   (void)hipMemsetAsync(base + L.red_count, 0, 4, st);
   for (int q = 0; q < NBUF; ++q) (void)hipMemsetAsync(base + L.buf[q], 0, (size_t)h.n * S.Rcap * (f32 ? 4 : 8), st);
@@ -1675,6 +1678,13 @@ static const int32_t *slot_ilist(Pool &P, int s) {
   return (const int32_t *)((char *)S.slab + L.ilist);
 }
 
+// A caller buffer can stand in for a work buffer when its rows are exactly
+// the bucket's rows (r = R, ld = R) and it is 16-byte aligned (the kernels
+// move 16-byte chunks).
+static bool in_place(const void *X, int r, int64_t ld, int R) {
+  return r == R && ld == R && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+}
+
 hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st) {
   Slot &S = *P.slots[s];
   std::string &err = P.err;
@@ -1683,22 +1693,26 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
     err = "r exceeds the handle's column capacity";
     return HALLAR_E_INVALID;
   }
-  S.prm.buf[RU] = 0;
+  // the caller's U is read in place when its rows are the bucket's rows
+  const bool u_direct = in_place(U, r, ldu, R);
+  S.prm.buf[RU] = u_direct ? NBUF : 0;
+  S.prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
   S.prm.beta = 0.0;
   if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
   const Tile *T_ = slot_tiles(P, s);
   const int nt = (int)S.hp.tiles.size();
   const int32_t *IL = slot_ilist(P, s);
   const InstDev *D = P.d_insts;
-  op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
-  // the SDDMM reads {p_l, b_l} in pair order: bring them up to date with p
-  if (S.hp.direct) op_refresh_pb(st, IL, 1, std::max<int64_t>(S.hp.npairs, S.hp.low_recompute ? S.hp.nlower : 0), D);
+  if (!u_direct) op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  // T does not depend on p: the epilogue's {p_l, b_l} reads (zeros at load,
+  // else the last solve's) only feed scalars this call does not return
   op_lr_dots(P.prec, R, st, T_, nt, D, RU);
-  op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0);
+  // direct mode: each constrained pair's lane writes T_l into the caller's T
+  op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0, S.hp.direct && S.hp.m > 0 ? T + 1 : nullptr);
   if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);
   op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
   HL_TRY(hipMemcpyAsync(T, &P.d_res[s].v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
-  if (S.hp.m > 0)
+  if (S.hp.m > 0 && !S.hp.direct)
     HL_TRY(hipMemcpyAsync(T + 1, S.dev.TY, sizeof(double) * S.hp.m, hipMemcpyDeviceToDevice, st), "T");
   HL_TRY(hipGetLastError(), "eval launch");
   return HALLAR_OK;
@@ -1713,21 +1727,30 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
     err = "r exceeds the handle's column capacity";
     return HALLAR_E_INVALID;
   }
-  S.prm.buf[RU] = 0;
-  S.prm.buf[RU2] = 1;
+  // U read and W written in place when their rows are the bucket's rows
+  // (and W does not overlap U: the SpMM gathers rows of U while writing W)
+  const bool u_direct = in_place(U, r, ldu, R);
+  const size_t esz = P.prec == 0 ? 8 : 4;
+  const uintptr_t u0 = reinterpret_cast<uintptr_t>(U), w0 = reinterpret_cast<uintptr_t>(W);
+  const bool overlap = u0 < w0 + (size_t)S.hp.n * ldw * esz && w0 < u0 + (size_t)S.hp.n * ldu * esz;
+  const bool w_direct = in_place(W, r, ldw, R) && !overlap;
+  S.prm.buf[RU] = u_direct ? NBUF : 0;
+  S.prm.buf[RU2] = w_direct ? NBUF + 1 : 1;
+  S.prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
+  S.prm.ext[1] = w_direct ? W : nullptr;
   if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
   const Tile *T_ = slot_tiles(P, s);
   const int nt = (int)S.hp.tiles.size();
   const int32_t *IL = slot_ilist(P, s);
   const InstDev *D = P.d_insts;
   op_pairvals(P.prec, st, IL, 1, (int)S.hp.npairs, D, 0, p, S.hp.direct ? 0 : 1);
-  op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  if (!u_direct) op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
   if (S.hp.r0 > 0) {
     op_lr_dots(P.prec, R, st, T_, nt, D, RU);
     op_reduce(st, IL, 1, D, RDH_LRONLY, 0, R, 0);
   }
   op_spmm(P.prec, R, st, T_, nt, D, RU, 0, 0, RU2, SPM_PLAIN);
-  op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);
+  if (!w_direct) op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);
   HL_TRY(hipGetLastError(), "adjoint launch");
   return HALLAR_OK;
 }

@@ -78,6 +78,7 @@ struct InstParams {
   uint64_t lz_seed;     // counter-based start-vector seed
   int64_t up_off;       // offset of this instance's coefficients in the upload buffer
   int64_t dl_off;       // offset of this instance's block in the download buffer
+  void *ext[2];         // caller buffers addressed as roles NBUF, NBUF + 1 (standalone operator calls)
 };
 
 // Per-instance scalars written by the kernels, read back by the host.

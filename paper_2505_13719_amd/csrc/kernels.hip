@@ -100,9 +100,13 @@ __device__ __forceinline__ void block_partials(double (&acc)[NQ], const InstDev 
   }
 }
 
+// Buffer of a role: one of the instance's n x R_cap work buffers, or (index
+// NBUF + k) the caller's buffer P.ext[k] that the standalone operator calls
+// read or write in place when its layout is the bucket's (ld = R).
 template <typename T>
 __device__ __forceinline__ T *role_ptr(const InstDev &I, const InstParams &P, int role) {
-  return reinterpret_cast<T *>(I.buf[P.buf[role]]);
+  const int b = P.buf[role];
+  return reinterpret_cast<T *>(b < NBUF ? I.buf[b] : P.ext[b - NBUF]);
 }
 
 
@@ -136,6 +140,7 @@ struct SddmmArgs {
   int32_t msel;      // 0: m_xt, 1: m_yp, -1: no pair values
   int32_t write_T;   // store T_l (l >= 1) in TY
   int32_t write_yp;  // store y'_l in yp
+  double *tout;      // non-null (one instance only): T_l goes to tout[l - 1] instead of TY
 };
 
 // Narrow rows (at most two 16-byte chunks): one thread per pair holds both
@@ -210,7 +215,7 @@ __device__ __forceinline__ void sddmm_narrow_pairs(const Tile &tl, const InstDev
           acc[1] += pl[u] * q.r;
           acc[2] += q.r * q.r;
           acc[3] += q.y * q.t;
-          if (a.write_T) I.TY[l[u] - 1] = q.t;
+          if (a.write_T) (a.tout ? a.tout : I.TY)[l[u] - 1] = q.t;
           if (a.write_yp) I.yp[l[u] - 1] = q.y;
           mv = q.m;
         }
@@ -352,7 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_sddmm(const Tile *__restrict__ tiles,
           acc[1] += pl[u] * q.r;
           acc[2] += q.r * q.r;
           acc[3] += q.y * q.t;
-          if (a.write_T) I.TY[l[u] - 1] = q.t;
+          if (a.write_T) (a.tout ? a.tout : I.TY)[l[u] - 1] = q.t;
           if (a.write_yp) I.yp[l[u] - 1] = q.y;
           mv = q.m;
         }
@@ -2004,9 +2009,9 @@ namespace hl {
 static bool is64(int prec) { return prec == 0; }
 
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT,
-              int wyp) {
+              int wyp, double *tout) {
   if (nt <= 0) return;
-  SddmmArgs a{xrole, msel, wT, wyp};
+  SddmmArgs a{xrole, msel, wT, wyp, tout};
   if (is64(prec)) HL_DISPATCH_G(double, R, l_sddmm, s, t, nt, d, a);
   else HL_DISPATCH_G(float, R, l_sddmm, s, t, nt, d, a);
 }

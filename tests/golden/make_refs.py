@@ -18,14 +18,14 @@ import sdp_instances as si  # noqa: E402
 
 
 def cases():
-    yield "maxcut_er800_s1", si.maxcut_er_800(1), dict(rank_cap=16), 1e-7
+    yield "maxcut_er800_s1", si.maxcut_er_800(1), dict(rank_cap=16, rank_cap_truncate=True), 1e-7
     rng = np.random.default_rng(11)
     i, j = si.er_edges(400, 0.02, rng)
     yield "maxcut_pm1_er400", si.maxcut_problem(400, i, j, si.pm1_weights(i.size, rng), name="maxcut_pm1_er400"), {}, 1e-7
     yield "torus_pm1_20x20", si.maxcut_torus(20, 20, seed=3), {}, 1e-6
     rng = np.random.default_rng(12)
     i, j = si.er_edges(150, 0.06, rng)
-    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-7
+    yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-6
     yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}, 1e-7
 
 

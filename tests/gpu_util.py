@@ -21,14 +21,16 @@ def normwise(x, ref, terms):
 
 
 def abs_terms_T(prob, U):
-    """Per-constraint sum of |(2 - delta) A_ij <U_i, U_j>| (plus |low-rank|)."""
-    import oracle  # noqa
+    """Per-constraint sum of the absolute values of every product that forms
+    T_l: sum over its entries of |(2 - delta) A_ij| sum_c |U_ic| |U_jc|, plus
+    sum_ab |D_ab| (|K|^T |U|)_a . (|K|^T |U|)_b for a low-rank term."""
+    A = np.abs(U)
     w = np.where(prob.row == prob.col, 1.0, 2.0) * np.abs(prob.val)
-    d = np.abs(np.einsum("kr,kr->k", U[prob.row], U[prob.col]))
+    d = np.einsum("kr,kr->k", A[prob.row], A[prob.col])
     out = np.bincount(prob.con, weights=w * d, minlength=prob.m + 1)
     for l, K, D in zip(prob.lr_con, prob.lr_K, prob.lr_D):
-        Y = K.T @ U
-        out[l] += float(np.abs(D * (Y @ Y.T)).sum())
+        Y = np.abs(K).T @ A
+        out[l] += float((np.abs(D) * (Y @ Y.T)).sum())
     return out
 
 
@@ -43,3 +45,20 @@ def abs_terms_W(prob, ptil, U):
     for l, K, D in zip(prob.lr_con, prob.lr_K, prob.lr_D):
         out = out + abs(ptil[l]) * (np.abs(K) @ (np.abs(D) @ (np.abs(K).T @ np.abs(U))))
     return out
+
+
+def entrywise(x, ref, terms, tol, u):
+    """max_k |x_k - ref_k| / (tol * terms_k + 4 u |ref_k|): <= 1 passes.
+    `terms` is the per-entry sum of absolute contributions, u the unit
+    roundoff of the stored result (an exact zero gets no slack)."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = tol * np.asarray(terms, np.float64) + 4.0 * u * np.abs(ref)
+    err = np.abs(x - ref)
+    bad = err > 0
+    if not bad.any():
+        return 0.0
+    return float(np.max(err[bad] / np.maximum(den[bad], 1e-300)))
+
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53

@@ -6,8 +6,10 @@ times (FP32-mixed, default tile schedule):
   entry points (eq. A tilde operator, Algorithms 2-5) against the FP64 oracle
   on every output -- the oracle's vectorised operators finish in seconds at
   these sizes -- with the FP32-mixed bar of the small-instance tests;
-* the full c3 solve, the path the benchmark times (fused trial kernel, split
-  reductions, recomputed lower half): its certificate is recomputed
+* the full c3 solve in FP64 and FP32-mixed, the path the benchmark times
+  (fused trial kernel, split reductions, recomputed lower half): its
+  objective is within 1e-5 of the closed-form optimum ||A B^T||_* (exact
+  recovery, Section 5.2), and its certificate is recomputed
   independently of the GPU -- the oracle evaluates C . UU^T and
   A(UU^T) - b from the returned U (eq. termination2), and scipy's eigsh
   computes lambda_min(C + A*(p)) for the dual value -b^T p -
@@ -29,7 +31,7 @@ import pytest
 
 import oracle
 import sdp_instances as si
-from gpu_util import abs_terms_T, abs_terms_W, dev, normwise, torch
+from gpu_util import U32, U64, abs_terms_T, abs_terms_W, dev, entrywise, normwise, torch
 from paper_2505_13719_amd import hallar as H
 
 pytestmark = pytest.mark.gpu
@@ -66,17 +68,29 @@ def test_fullsize_operators(name, r):
     finally:
         H.hallar_destroy(h)
     Uo = U.astype(np.float64)  # the exact values the GPU multiplied
-    assert normwise(T, oracle.a_tilde(prob, Uo), abs_terms_T(prob, Uo)) <= TOL_FP32
+    Tref, tT = oracle.a_tilde(prob, Uo), abs_terms_T(prob, Uo)
+    assert normwise(T, Tref, tT) <= TOL_FP32
+    assert entrywise(T, Tref, tT, TOL_FP32, U64) <= 1.0
     ptil = np.concatenate([[1.0], p])
-    assert normwise(W, oracle.adjoint_apply(prob, ptil, Uo), abs_terms_W(prob, ptil, Uo)) <= TOL_FP32
+    Wref, tW = oracle.adjoint_apply(prob, ptil, Uo), abs_terms_W(prob, ptil, Uo)
+    assert normwise(W, Wref, tW) <= TOL_FP32
+    assert entrywise(W, Wref, tW, TOL_FP32, U32) <= 1.0
 
 
-def test_fullsize_mc_solve_certificate():
+def nuclear_norm(A, B):
+    """||A B^T||_* from QR factors of the thin A and B and an r x r SVD."""
+    _, ra = np.linalg.qr(A)
+    _, rb = np.linalg.qr(B)
+    return float(np.linalg.svd(ra @ rb.T, compute_uv=False).sum())
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED], ids=["fp64", "fp32_mixed"])
+def test_fullsize_mc_solve_certificate(prec):
     import scipy.sparse.linalg as sla
     d = dev()
     prob = _instance("mc_1e5x1e5_r3")
-    print(f"[fullsize] mc solve: n={prob.n} m={prob.m}", flush=True)
-    h = H.hallar_create(prob, H.FP32_MIXED, H.options(eps=1e-5, rank_cap=16))
+    print(f"[fullsize] mc solve: n={prob.n} m={prob.m} prec={prec}", flush=True)
+    h = H.hallar_create(prob, prec, H.options(eps=1e-5, rank_cap=16))
     try:
         res = H.hallar_solve(h, torch.tensor(si.gaussian_u0(prob.n, 7), device=d))
         assert res["status"] == "ok", res
@@ -104,3 +118,8 @@ def test_fullsize_mc_solve_certificate():
     gap = abs(pval - dval) / (1.0 + abs(pval) + abs(dval))
     print(f"[fullsize] theta {res['theta']:.10g} exact {theta:.10g}; gap {res['gap']:.3e} exact {gap:.3e}", flush=True)
     assert gap <= 1e-5 * (1.0 + 1e-6), (gap, pval, dval, theta, res["theta"])
+    # exact recovery (Section 5.2, eq. matcomp-sdp): noise-free with
+    # m = 20 r (n1 + n2) observed entries the SDP's optimum is ||A B^T||_*
+    nuc = nuclear_norm(prob.meta["A"], prob.meta["B"])
+    print(f"[fullsize] pval {pval:.6f} nuclear norm {nuc:.6f} rel {(pval - nuc) / (1 + nuc):.3e}", flush=True)
+    assert abs(pval - nuc) <= 1e-5 * (1.0 + nuc), (pval, nuc)

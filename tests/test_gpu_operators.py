@@ -1,8 +1,10 @@
 """GPU parity of the operator entry points against the FP64 oracle.
 
 hallar_eval_AUUt (A~(UU^T), Algorithms 2-3) and hallar_adjoint_spmm
-(A~*(1,p)U, Algorithms 4-5) through the C ABI, in FP64 (normwise error
-<= 1e-12 of the absolute terms) and FP32-mixed (<= 1e-5), on instances that
+(A~*(1,p)U, Algorithms 4-5) through the C ABI, in FP64 (error <= 1e-12 of
+the absolute terms) and FP32-mixed (<= 1e-5), normwise and entry by entry
+(each output within tol times its own absolute terms plus 4 units of
+roundoff of the stored result), on instances that
 span several tiles with ragged tails: general multi-entry constraints,
 MaxCut on ER graphs and tori, Lovasz theta with the low-rank objective,
 matrix completion; edge cases r = 1, r = 64, ldu > r, n = 1, m = 0.
@@ -12,12 +14,13 @@ import pytest
 
 import oracle
 import sdp_instances as si
-from gpu_util import abs_terms_T, abs_terms_W, dev, normwise, torch
+from gpu_util import U32, U64, abs_terms_T, abs_terms_W, dev, entrywise, normwise, torch
 from paper_2505_13719_amd import hallar as H
 
 pytestmark = pytest.mark.gpu
 
 TOL = {H.FP64: 1e-12, H.FP32_MIXED: 1e-5}
+UNIT = {H.FP64: U64, H.FP32_MIXED: U32}
 
 
 def _cases():
@@ -49,13 +52,17 @@ def test_eval_and_adjoint_parity(prec, name, prob, r):
         H.hallar_eval_AUUt(h, Ud, T)
         Uo = Ud.double().cpu().numpy()       # the exact values the GPU multiplied
         Tref = oracle.a_tilde(prob, Uo)
-        assert normwise(T.cpu().numpy(), Tref, abs_terms_T(prob, Uo)) <= TOL[prec]
+        tT = abs_terms_T(prob, Uo)
+        assert normwise(T.cpu().numpy(), Tref, tT) <= TOL[prec]
+        assert entrywise(T.cpu().numpy(), Tref, tT, TOL[prec], U64) <= 1.0
         pd = torch.tensor(p, dtype=torch.float64, device=d)
         W = torch.empty((prob.n, r), dtype=dt, device=d)
         H.hallar_adjoint_spmm(h, pd, Ud, W)
         ptil = np.concatenate([[1.0], p])
         Wref = oracle.adjoint_apply(prob, ptil, Uo)
-        assert normwise(W.double().cpu().numpy(), Wref, abs_terms_W(prob, ptil, Uo)) <= TOL[prec]
+        tW = abs_terms_W(prob, ptil, Uo)
+        assert normwise(W.double().cpu().numpy(), Wref, tW) <= TOL[prec]
+        assert entrywise(W.double().cpu().numpy(), Wref, tW, TOL[prec], UNIT[prec]) <= 1.0
     finally:
         H.hallar_destroy(h)
 
@@ -140,5 +147,35 @@ def test_repeatable_bitwise():
         H.hallar_eval_AUUt(h, U, T1)
         H.hallar_eval_AUUt(h, U, T2)
         assert torch.equal(T1, T2)
+    finally:
+        H.hallar_destroy(h)
+
+
+@pytest.mark.parametrize("prec,r", [(H.FP32_MIXED, 4), (H.FP32_MIXED, 16), (H.FP64, 2), (H.FP64, 8)])
+def test_in_place_matches_packed(prec, r):
+    """With r a column bucket and ld = r the entry points read U and write W
+    in place; a strided view of the same values goes through the packing
+    copy.  Both run the same kernels on the same rows: identical bits."""
+    d = dev()
+    dt = torch.float64 if prec == H.FP64 else torch.float32
+    prob = si.mc_planted(500, 700, 3, 40000, seed=5)
+    rng = np.random.default_rng(2)
+    h = H.hallar_create(prob, prec)
+    try:
+        U = torch.tensor(rng.standard_normal((prob.n, r)), dtype=dt, device=d)
+        big = torch.zeros((prob.n, r + 3), dtype=dt, device=d)
+        big[:, :r] = U
+        Us = big[:, :r]
+        p = torch.tensor(rng.standard_normal(prob.m), device=d)
+        out = []
+        for X in (U, Us):
+            T = torch.empty(prob.m + 1, dtype=torch.float64, device=d)
+            H.hallar_eval_AUUt(h, X, T)
+            W = torch.empty((prob.n, r), dtype=dt, device=d)
+            H.hallar_adjoint_spmm(h, p, X, W)
+            out.append((T.cpu(), W.cpu()))
+        assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+        Uo = U.double().cpu().numpy()
+        assert normwise(out[0][0].numpy(), oracle.a_tilde(prob, Uo), abs_terms_T(prob, Uo)) <= TOL[prec]
     finally:
         H.hallar_destroy(h)
