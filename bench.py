@@ -14,6 +14,8 @@ synthetic instance resident in HBM.  Workloads (--workload):
           rank grows with n far beyond 32)
   er800   MaxCut SDP, G(800, 0.02), unit weights, FP64, rank cap 16
   theta   Lovasz theta SDP, G(5e4, avg deg 10), FP32-mixed, rank cap 64
+  hamming Lovasz theta SDP of the Hamming graph H(20, 2) (n = 2^20,
+          m = 10,485,760 edge constraints), FP64; theta = n/2 exactly
   served  stream of MaxCut requests (n log-uniform in [100, 2e4], deg 8,
           +-1 weights) through the continuous-batching pool; reports p50/p99
   ops     operator-level timing (SDDMM and SpMM entry points, --ops-instance
@@ -45,6 +47,13 @@ def workload(name):
     if name == "theta":
         return si.theta_er(50_000, 10.0, seed=3), H.FP32_MIXED, dict(rank_cap=64), \
             {"workload": "theta_er_50000_deg10", "n": 50_000, "rank_cap": 64}
+    if name == "hamming":
+        # Table tab:reduced_hamming_graphs: H(20, 2), theta = n/2
+        d = 20
+        n = 1 << d
+        prob = si.theta_problem(n, *si.hypercube_edges(d), name="hamming_20_2")
+        prob.meta["optimum"] = -n / 2
+        return prob, H.FP64, {}, {"workload": "theta_hamming_H(20,2)", "n": n, "m": int(prob.m)}
     if name == "mc":
         n1 = n2 = 100_000
         return si.mc_planted(n1, n2, 3, 20 * 3 * (n1 + n2), seed=4), H.FP64, dict(rank_cap=16), \
@@ -202,7 +211,7 @@ def timed_solves(prob, prec, kw, steps, warmup, args, label):
 
     dev = torch.device("cuda:0")
     opts = H.options(eps=1e-5, profile=args.profile, time_limit=3000.0, verbose=args.verbose, autotune=args.autotune,
-                     **kw)
+                     graphs=args.graphs, **kw)
     t_build = time.perf_counter()
     h = H.hallar_create(prob, prec, opts)
     t_build = time.perf_counter() - t_build
@@ -229,8 +238,11 @@ def timed_solves(prob, prec, kw, steps, warmup, args, label):
 def closed_form_optimum(prob):
     """The SDP's optimum where a closed form is known: noise-free matrix
     completion with exact recovery (||A B^T||_* from QR factors and an r x r
-    SVD).  None otherwise."""
+    SVD), and theta of a perfect graph (n/2 for the bipartite H(d, 2)).  None
+    otherwise."""
     import numpy as np
+    if "optimum" in prob.meta:
+        return float(prob.meta["optimum"])
     if "A" not in prob.meta:
         return None
     _, ra = np.linalg.qr(prob.meta["A"])
@@ -311,7 +323,7 @@ def bench_served(args):
     reqs = [si.served_request(k, int(n), seed=5) for k, n in enumerate(sizes)]
     U0s = [si.gaussian_u0(int(n), 1000 + k) for k, n in enumerate(sizes)]
     t_gen = time.perf_counter() - t_gen
-    opts = H.options(eps=1e-5, profile=args.profile, verbose=args.verbose)
+    opts = H.options(eps=1e-5, profile=args.profile, verbose=args.verbose, graphs=args.graphs)
     rate = args.rate
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq)) if rate > 0 else np.zeros(nreq)
     pool = H.hallar_pool_create(int(args.budget_gb * (1 << 30)), args.max_active, H.FP32_MIXED, opts)
@@ -390,8 +402,9 @@ def bench_served(args):
 
 
 def bench_ops(args):
-    """Operator-level timing on the instance of --ops-instance (FP32-mixed;
-    r = 4 for matrix completion, 32 for the torus): hallar_eval_AUUt (SDDMM +
+    """Operator-level timing on the instance of --ops-instance (the workload's
+    precision unless --precision; r = 4 for matrix completion, 32 for the
+    torus, both column buckets, so U and W are used in place): hallar_eval_AUUt (SDDMM +
     AL epilogue) and hallar_adjoint_spmm (SpMM), each called --steps times on a
     random U, plus a plain 1 GiB device copy (the calibration kernel for the
     HBM byte counters)."""
@@ -401,11 +414,14 @@ def bench_ops(args):
     from paper_2505_13719_amd import hallar as H
 
     prob, prec, kw, cfg = workload(args.ops_instance)
+    if args.precision:
+        prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
+    dt = torch.float64 if prec == H.FP64 else torch.float32
     dev = torch.device("cuda:0")
     r = 4 if args.ops_instance == "mc" else 32
     h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, **kw))
     g = torch.Generator(device="cpu").manual_seed(0)
-    U = (torch.randn((prob.n, r), generator=g, dtype=torch.float32) / math.sqrt(r)).to(dev)
+    U = (torch.randn((prob.n, r), generator=g, dtype=dt) / math.sqrt(r)).to(dev)
     W = torch.empty_like(U)
     T = torch.empty(prob.m + 1, dtype=torch.float64, device=dev)
     p = torch.tensor(np.random.default_rng(1).standard_normal(prob.m), device=dev)
@@ -429,7 +445,8 @@ def bench_ops(args):
         out[name] = round(e0.elapsed_time(e1) * 1e3 / args.steps, 2)
         print(f"[bench] {name}: {out[name]} us/call", file=sys.stderr, flush=True)
     H.hallar_destroy(h)
-    return {"metric": "operator us/call", "config": dict(cfg, r=r), "us_per_call": out,
+    return {"metric": "operator us/call", "config": dict(cfg, r=r, precision="fp64" if prec == H.FP64 else "fp32_mixed"),
+            "us_per_call": out,
             "copy_gbs": round(2 * (1 << 30) / (out["copy_1GiB"] * 1e-6) / 1e9, 1)}
 
 
@@ -438,13 +455,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mc", choices=["torus", "er800", "theta", "mc", "served", "ops"])
+    ap.add_argument("--workload", default="mc", choices=["torus", "er800", "theta", "mc", "hamming", "served", "ops"])
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0, help="solver progress on stderr (1: outer, 2: HLR)")
-    ap.add_argument("--profile", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--profile", type=int, default=2, choices=[0, 1, 2],
                     help="HIP-event timing inside the timed solves: 2 = the sparse kernel classes only (default, "
-                         "least overhead), 1 = every class")
+                         "least overhead), 1 = every class, 0 = none (repeating rounds then replay captured graphs)")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1], help="opts.graphs (used when --profile 0)")
     ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
     ap.add_argument("--autotune", type=int, default=0, help="1: tune the tile schedule at create (timed outside the steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)

@@ -127,6 +127,14 @@ typedef struct {
   int32_t rank_cap_truncate;        /* 1: at the rank cap keep the cap's largest directions of Y Y^T and
                                        count each such truncation in n_truncations (X changes); 0
                                        (default): stop with HALLAR_E_RANK_CAP */
+  int32_t graphs;                   /* 1: a round of kernel launches of one operation group that repeats
+                                       one seen before (same operation, instances, buckets and tile
+                                       ranges) is replayed as a captured HIP graph instead of being
+                                       enqueued kernel by kernel; same kernels in the same order, so the
+                                       same bits.  Rounds of several groups (batches, the serving pool)
+                                       and rounds while opts.profile times kernel classes are enqueued
+                                       directly.  0 (default): always enqueue directly */
+  int32_t pad_;
 } hallar_options;
 
 void hallar_default_options(hallar_options *opts);
@@ -149,6 +157,7 @@ typedef struct {
   int64_t n_hlr_iters, n_eig_calls, n_truncations, n_rounds;
   double obj_bound;      /* |pval - dval| + |p^T (A(X) - b)| at the last outer iteration: an
                             a-posteriori estimate of |pval - P*| (see opts.obj_check) */
+  int64_t n_graph_rounds;/* rounds of n_rounds whose kernels ran as a replayed graph (opts.graphs) */
 } hallar_result;
 
 typedef struct {

@@ -47,6 +47,7 @@ bool check_opts(const hallar_options &o, std::string &msg) {
   if (o.unfused_trial != 0 && o.unfused_trial != 1) { msg = "opts.unfused_trial must be 0 or 1"; return false; }
   if (o.obj_check != 0 && o.obj_check != 1) { msg = "opts.obj_check must be 0 or 1"; return false; }
   if (o.rank_cap_truncate != 0 && o.rank_cap_truncate != 1) { msg = "opts.rank_cap_truncate must be 0 or 1"; return false; }
+  if (o.graphs != 0 && o.graphs != 1) { msg = "opts.graphs must be 0 or 1"; return false; }
   if (o.profile < 0 || o.profile > 2) { msg = "opts.profile must be 0, 1 or 2"; return false; }
   if (o.fista_max_iter < 1 || o.aipp_max_iter < 1 || o.hlr_max_iter < 1 || o.outer_max_iter < 1 || o.eig_max_iter < 1) {
     msg = "iteration caps must be >= 1";
@@ -98,6 +99,7 @@ void hallar_default_options(hallar_options *o) {
   o->verbose = 0;
   o->obj_check = 1;
   o->rank_cap_truncate = 0;
+  o->graphs = 0;
 }
 
 const char *hallar_last_error(hallar_t h) { return h ? h->err.c_str() : g_err.c_str(); }

@@ -265,6 +265,11 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
     HL_TRY(hipEventCreateWithFlags(&P.ev_join[q], hipEventDisableTiming), "hipEventCreate");
   }
   HL_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming), "hipEventCreate");
+  if (opts.graphs) {
+    HL_TRY(hipStreamCreateWithFlags(&P.gst, hipStreamNonBlocking), "hipStreamCreate");
+    HL_TRY(hipEventCreateWithFlags(&P.ev_gfork, hipEventDisableTiming), "hipEventCreate");
+    HL_TRY(hipEventCreateWithFlags(&P.ev_gjoin, hipEventDisableTiming), "hipEventCreate");
+  }
   P.profile = opts.profile != 0;
   P.prof_level = opts.profile;
   if (P.profile) {
@@ -281,9 +286,15 @@ hallar_status pool_init(Pool &P, int max_slots, int prec, const hallar_options &
 
 void pool_release(Pool &P) {
   if (P.opts.verbose && P.rounds > 0)
-    fprintf(stderr, "[hallar] pool: %lld rounds, host seconds prep %.3f launch %.3f wait %.3f resume %.3f\n",
-            (long long)P.rounds, P.t_prep, P.t_launch, P.t_wait, P.t_resume);
+    fprintf(stderr,
+            "[hallar] pool: %lld rounds (%lld replayed as graphs, %lld captured), host seconds prep %.3f launch %.3f "
+            "wait %.3f resume %.3f\n",
+            (long long)P.rounds, (long long)P.graph_replays, (long long)P.graph_captures, P.t_prep, P.t_launch,
+            P.t_wait, P.t_resume);
   P.workers.reset();
+  for (auto &kv : P.graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  P.graphs.clear();
   for (int s = 0; s < (int)P.slots.size(); ++s)
     if (P.slots[s]) slot_unload(P, s);
   auto fr = [](void *p) {
@@ -304,6 +315,11 @@ void pool_release(Pool &P) {
   }
   if (P.ev_fork) (void)hipEventDestroy(P.ev_fork);
   P.ev_fork = nullptr;
+  if (P.gst) (void)hipStreamDestroy(P.gst);
+  if (P.ev_gfork) (void)hipEventDestroy(P.ev_gfork);
+  if (P.ev_gjoin) (void)hipEventDestroy(P.ev_gjoin);
+  P.gst = nullptr;
+  P.ev_gfork = P.ev_gjoin = nullptr;
   P.d_insts = nullptr;
   P.arena.release();
 }
@@ -922,23 +938,118 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     P.ilist_dev.assign(P.h_ilist, P.h_ilist + ipos);
   }
   if (up_used) HL_TRY(hipMemcpyAsync(P.d_up, P.h_up, sizeof(double) * up_used, hipMemcpyHostToDevice, st), "upload coef");
-  if (groups.size() == 1) {
-    launch_group(P, groups[0], st);
-  } else {
-    // groups touch disjoint instances: spread them over the main and side
-    // streams, all after the uploads above, all joined before the downloads
-    HL_TRY(hipEventRecord(P.ev_fork, st), "fork");
-    const int ns = std::min<int>((int)groups.size(), 1 + Pool::NSIDE);
-    for (int q = 1; q < ns; ++q) HL_TRY(hipStreamWaitEvent(P.side[q - 1], P.ev_fork, 0), "fork wait");
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
-      const int q = (int)(gi % ns);
-      launch_group(P, groups[gi], q == 0 ? st : P.side[q - 1]);
+  auto launch_all = [&](hipStream_t ms) -> hallar_status {
+    if (groups.size() == 1) {
+      launch_group(P, groups[0], ms);
+    } else {
+      // groups touch disjoint instances: spread them over the main and side
+      // streams, all after the uploads above, all joined before the downloads
+      HL_TRY(hipEventRecord(P.ev_fork, ms), "fork");
+      const int ns = std::min<int>((int)groups.size(), 1 + Pool::NSIDE);
+      for (int q = 1; q < ns; ++q) HL_TRY(hipStreamWaitEvent(P.side[q - 1], P.ev_fork, 0), "fork wait");
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const int q = (int)(gi % ns);
+        launch_group(P, groups[gi], q == 0 ? ms : P.side[q - 1]);
+      }
+      for (int q = 1; q < ns; ++q) {
+        HL_TRY(hipEventRecord(P.ev_join[q - 1], P.side[q - 1]), "join");
+        HL_TRY(hipStreamWaitEvent(ms, P.ev_join[q - 1], 0), "join wait");
+      }
     }
-    for (int q = 1; q < ns; ++q) {
-      HL_TRY(hipEventRecord(P.ev_join[q - 1], P.side[q - 1]), "join");
-      HL_TRY(hipStreamWaitEvent(st, P.ev_join[q - 1], 0), "join wait");
+    return HALLAR_OK;
+  };
+  // The kernel section of a round reads everything that changes from one
+  // round to the next (parameters, tiles, instance lists, coefficients) from
+  // device memory uploaded above, so a round whose launches are decided by
+  // the same inputs (op codes and fields, groups, buckets, tile and instance
+  // ranges, loaded instances) replays the graph captured from the first such
+  // round instead of enqueuing its kernels one by one.  Captured on the second
+  // occurrence; not used while kernel classes are timed (opts.profile).
+  // Only rounds of one group are captured (a linear chain of kernels on the
+  // graph stream, no events inside the graph): a batched solve whose
+  // multi-group rounds were captured with their side-stream fork and join
+  // ended in a host segmentation fault, cause not found, so that form is off.
+  bool launched = false, direct_on_gst = false;
+  if (P.opts.graphs && !P.profile && P.gst && groups.size() == 1) {
+    std::vector<int64_t> sig;
+    sig.reserve(32 * groups.size() + 8);
+    sig.push_back(P.tile_epoch);
+    sig.push_back((int64_t)(uintptr_t)P.d_tiles);
+    sig.push_back((int64_t)(uintptr_t)P.d_ilist);
+    sig.push_back((int64_t)(uintptr_t)P.d_insts);
+    for (const Group &g : groups) {
+      const PendingOp &o = *g.op;
+      const int64_t f[] = {g.code, g.R, g.R2, g.steps, g.t0, g.nt, g.i0, g.ni, g.gi0, g.gni, g.di0, g.dni, g.maxm,
+                           g.maxp, o.xrole, o.msel, o.wT, o.wyp, o.zsel, o.src, o.dst,
+                           (int64_t)(uintptr_t)o.ext, o.ext_r, o.ext_ld, (int64_t)g.slots.size()};
+      sig.insert(sig.end(), std::begin(f), std::end(f));
+      sig.insert(sig.end(), g.slots.begin(), g.slots.end());
+    }
+    uint64_t hsh = 1469598103934665603ull;
+    for (int64_t v : sig) hsh = (hsh ^ (uint64_t)v) * 1099511628211ull;
+    Pool::RoundGraph &rg = P.graphs[hsh];
+    if (rg.sig != sig) {
+      // a new signature (or a hash collision): start over for this key
+      if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
+      rg = Pool::RoundGraph{};
+      rg.sig = sig;
+    }
+    rg.last_use = P.rounds;
+    const bool want = !rg.exec && !rg.failed && ++rg.seen >= 2;
+    if (want || rg.exec) {
+      // the graph runs on its own stream, after the uploads on `st`
+      HL_TRY(hipEventRecord(P.ev_gfork, st), "graph fork");
+      HL_TRY(hipStreamWaitEvent(P.gst, P.ev_gfork, 0), "graph fork wait");
+    }
+    if (want) {
+      hipGraph_t graph = nullptr;
+      bool ok = hipStreamBeginCapture(P.gst, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        const hallar_status ls = launch_all(P.gst);
+        ok = hipStreamEndCapture(P.gst, &graph) == hipSuccess && ls == HALLAR_OK && graph;
+      }
+      if (ok) ok = hipGraphInstantiate(&rg.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (!ok) {
+        rg.exec = nullptr;
+        rg.failed = true;  // this signature launches directly from now on
+      } else {
+        P.graph_captures++;
+      }
+    }
+    if (rg.exec) {
+      HL_TRY(hipGraphLaunch(rg.exec, P.gst), "graph launch");
+      P.graph_replays++;
+      launched = true;
+    } else if (want) {
+      // capture failed: this round's kernels go directly onto the graph stream
+      const hallar_status ls = launch_all(P.gst);
+      if (ls != HALLAR_OK) return ls;
+      launched = true;
+      direct_on_gst = true;
+    }
+    if (launched) {
+      HL_TRY(hipEventRecord(P.ev_gjoin, P.gst), "graph join");
+      HL_TRY(hipStreamWaitEvent(st, P.ev_gjoin, 0), "graph join wait");
+    }
+    if (P.graphs.size() > 512) {
+      // keep the cache bounded: drop the graphs unused for longest
+      std::vector<std::pair<int64_t, uint64_t>> age;
+      for (auto &kv : P.graphs) age.emplace_back(kv.second.last_use, kv.first);
+      std::sort(age.begin(), age.end());
+      for (size_t k = 0; k < age.size() / 2; ++k) {
+        auto it = P.graphs.find(age[k].second);
+        if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+        P.graphs.erase(it);
+      }
     }
   }
+  if (!launched) {
+    const hallar_status ls = launch_all(st);
+    if (ls != HALLAR_OK) return ls;
+  }
+  if (direct_on_gst) launched = false;  // counts replays only
   HL_TRY(hipGetLastError(), "kernel launch");
   HL_TRY(hipMemcpyAsync(P.h_res, P.d_res, sizeof(InstRes) * maxs, hipMemcpyDeviceToHost, st), "download results");
   if (dl_used) HL_TRY(hipMemcpyAsync(P.h_dl, P.d_dl, sizeof(double) * dl_used, hipMemcpyDeviceToHost, st), "download");
@@ -954,6 +1065,7 @@ static hallar_status run_round(Pool &P, bool &did_work) {
     Slot &S = *P.slots[run[i]];
     S.has_op = false;
     S.result.n_rounds++;
+    if (launched) S.result.n_graph_rounds++;
     if (S.op.dl_count) S.dl.assign(P.h_dl + S.op.dl_off, P.h_dl + S.op.dl_off + S.op.dl_count);
     auto h = S.resume;
     S.resume = {};

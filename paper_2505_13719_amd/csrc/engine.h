@@ -3,6 +3,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <unordered_map>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -113,6 +114,22 @@ struct Pool {
   std::unique_ptr<ResumeWorkers> workers;
   // host-side seconds per round phase (reported at release when opts.verbose)
   double t_prep = 0, t_launch = 0, t_wait = 0, t_resume = 0;
+  // captured rounds (opts.graphs): the kernel section of a round, keyed by
+  // everything that decides its launches, replayed as one graph launch
+  struct RoundGraph {
+    std::vector<int64_t> sig;
+    hipGraphExec_t exec = nullptr;
+    int seen = 0;
+    bool failed = false;
+    int64_t last_use = 0;
+  };
+  std::unordered_map<uint64_t, RoundGraph> graphs;
+  // stream the graphs are captured on and replayed from (the caller's stream
+  // may be the null stream, which cannot be captured), forked from and
+  // joined back to `stream` by events
+  hipStream_t gst = nullptr;
+  hipEvent_t ev_gfork = nullptr, ev_gjoin = nullptr;
+  int64_t graph_replays = 0, graph_captures = 0;
 };
 
 // lifetime

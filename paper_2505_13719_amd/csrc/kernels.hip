@@ -819,7 +819,10 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
   static_assert(G <= 2, "the fused trial kernel takes narrow rows");
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  constexpr int UN = 4;
+  // entries in flight per lane: four for one-chunk rows, two for two-chunk
+  // rows (measured on matrix completion: FP32 rank 4 260 / 272 us with four /
+  // two, FP64 rank 4 351 / 316 us; eight costs registers and occupancy)
+  constexpr int UN = G == 1 ? 4 : 2;
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];

@@ -43,7 +43,7 @@ class hallar_options(C.Structure):
                 ("rank_cap", C.c_int32), ("drop_tol", C.c_double), ("time_limit", C.c_double),
                 ("seed", C.c_uint64), ("verbose", C.c_int32), ("profile", C.c_int32), ("autotune", C.c_int32),
                 ("lower_gather", C.c_int32), ("unfused_trial", C.c_int32), ("obj_check", C.c_int32),
-                ("rank_cap_truncate", C.c_int32)]
+                ("rank_cap_truncate", C.c_int32), ("graphs", C.c_int32), ("pad_", C.c_int32)]
 
 
 class hallar_result(C.Structure):
@@ -53,7 +53,7 @@ class hallar_result(C.Structure):
                 ("n_sddmm", C.c_int64), ("n_spmm", C.c_int64), ("n_matvec", C.c_int64),
                 ("n_fista_trials", C.c_int64), ("n_aipp_iters", C.c_int64), ("n_hlr_iters", C.c_int64),
                 ("n_eig_calls", C.c_int64), ("n_truncations", C.c_int64), ("n_rounds", C.c_int64),
-                ("obj_bound", C.c_double)]
+                ("obj_bound", C.c_double), ("n_graph_rounds", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}

@@ -27,6 +27,11 @@ def cases():
     i, j = si.er_edges(150, 0.06, rng)
     yield "theta_er150", si.theta_problem(150, i, j), {}, 1e-6
     yield "mc_60x90", si.mc_planted(60, 90, 2, 2500, seed=6), {}, 1e-7
+    # the +-1 MaxCut requests of the serving pool test (ER, average degree 8)
+    rng = np.random.default_rng(5)
+    for n in (37, 150, 420, 1100):
+        i, j = si.er_edges(n, 8.0 / (n - 1), rng)
+        yield f"pool_er{n}", si.maxcut_problem(n, i, j, si.pm1_weights(i.size, rng)), {}, 1e-7
 
 
 def main(only):

