@@ -199,6 +199,22 @@ hallar_status hallar_describe(hallar_t h, int64_t *pairs, int64_t *sym_nnz, int6
  * otherwise it is first copied into a zero-padded work buffer. */
 hallar_status hallar_eval_AUUt(hallar_t h, const void *U, int32_t r, int64_t ldu, double *T, void *stream);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same T = A~(U U^T) as hallar_eval_AUUt, same arguments, layouts and
+ * bits, but everything the evaluation writes besides T (a copy of the
+ * handle's descriptor and parameters, result scalars, per-tile partial
+ * sums, the packed U when U is not used in place, low-rank products and, for
+ * instances with multi-entry constraints, per-pair dot products and T, y'
+ * staging) lives in one static device array of 64 MiB per GPU, held until
+ * the process ends; the handle's own workspace is not touched.  The call
+ * allocates nothing and returns E_INVALID if the instance needs more
+ * scratch than that (about 8 bytes per partial-sum slot and tile, plus
+ * n r_pad operator words when U is packed).  Every call on a GPU shares
+ * that GPU's array, so calls that overlap on one GPU (different streams or
+ * threads) race; calls ordered on one stream do not. */
+hallar_status hallar_eval_AUUt_noalloc(hallar_t h, const void *U, int32_t r, int64_t ldu, double *T, void *stream);
+
 /* W = A~*(1, p) U = (C + sum_l p_l A_l) U (Section 4.2, eq. Adjoint
  * calculation; Algorithms 4 and 5).  p: device double[m].  U as above; W:
  * device n x r, leading dimension ldw >= r, operator type.  Asynchronous.

@@ -243,6 +243,9 @@ hallar_status hallar_create(const hallar_problem *prob, hallar_precision prec, c
     return fail(nullptr, st, msg);
   }
   h->P.slots[0]->seed = o.seed;
+  // the allocation-free evaluation's scratch: its device address on this
+  // device, resolved once per device
+  if (hl::noalloc_scratch(&h->P.scratch) != hipSuccess) h->P.scratch = nullptr;
   *out = h;
   return HALLAR_OK;
 }
@@ -278,6 +281,15 @@ hallar_status hallar_eval_AUUt(hallar_t h, const void *U, int32_t r, int64_t ldu
   if (!U || !T) return fail(h, HALLAR_E_INVALID, "U and T must be device pointers");
   if (r < 1 || r > hl::R_MAX || ldu < r) return fail(h, HALLAR_E_INVALID, "need 1 <= r <= 64 and ldu >= r");
   const hallar_status st = hl::op_eval_AUUt(h->P, 0, U, r, ldu, T, (hipStream_t)stream);
+  if (st != HALLAR_OK) return fail(h, st, h->P.err);
+  return HALLAR_OK;
+}
+
+hallar_status hallar_eval_AUUt_noalloc(hallar_t h, const void *U, int32_t r, int64_t ldu, double *T, void *stream) {
+  if (!h || !h->P.slots[0]) return fail(h, HALLAR_E_INVALID, "bad handle");
+  if (!U || !T) return fail(h, HALLAR_E_INVALID, "U and T must be device pointers");
+  if (r < 1 || r > hl::R_MAX || ldu < r) return fail(h, HALLAR_E_INVALID, "need 1 <= r <= 64 and ldu >= r");
+  const hallar_status st = hl::op_eval_AUUt_noalloc(h->P, 0, U, r, ldu, T, (hipStream_t)stream);
   if (st != HALLAR_OK) return fail(h, st, h->P.err);
   return HALLAR_OK;
 }

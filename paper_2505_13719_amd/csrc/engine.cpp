@@ -1830,6 +1830,86 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
   return HALLAR_OK;
 }
 
+// The same evaluation with everything it writes besides T inside the
+// scratch array (no allocation, nothing of the handle's workspace touched):
+// the descriptor is copied on the device, so nothing host-side has to stay
+// alive after the call returns.  Calls that overlap on one GPU share the
+// array and race.
+hallar_status op_eval_AUUt_noalloc(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st) {
+  Slot &S = *P.slots[s];
+  std::string &err = P.err;
+  const int R = r_bucket(r, P.prec);
+  if (R > S.Rcap) {
+    err = "r exceeds the handle's column capacity";
+    return HALLAR_E_INVALID;
+  }
+  if (!P.scratch) {
+    err = "the scratch array's device address is unknown on this device";
+    return HALLAR_E_HIP;
+  }
+  const HostProblem &h = S.hp;
+  const bool u_direct = in_place(U, r, ldu, R);
+  const int nt = (int)h.tiles.size();
+  const int prows = (int)prows_for(h);
+  const int nslot = 4 + h.r0 * R;  // SDDMM sums, low-rank products
+  // carve the scratch (256-byte aligned pieces)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_insts = take(sizeof(InstDev) * (size_t)(s + 1));
+  const size_t o_prm = take(sizeof(InstParams));
+  const size_t o_res = take(sizeof(InstRes));
+  const size_t o_part = take(sizeof(double) * (size_t)nslot * prows);
+  const size_t o_u = take(u_direct ? 0 : (size_t)h.n * R * (P.prec == 0 ? 8 : 4));
+  const size_t o_z0 = take(sizeof(double) * 2 * LR_MAX * R_MAX);
+  const size_t o_ty = take(h.direct ? 0 : sizeof(double) * (size_t)h.m);
+  const size_t o_yp = take(h.direct ? 0 : sizeof(double) * (size_t)h.m);
+  const size_t o_bp = take(h.direct ? 0 : sizeof(double) * (size_t)h.npairs);
+  if (off > NOALLOC_SCRATCH_BYTES) {
+    err = "the evaluation needs " + std::to_string(off) + " bytes of scratch, more than the " +
+          std::to_string(NOALLOC_SCRATCH_BYTES) + " the allocation-free entry point has";
+    return HALLAR_E_INVALID;
+  }
+  char *base = static_cast<char *>(P.scratch);
+  NoallocViews v{};
+  v.insts = reinterpret_cast<InstDev *>(base + o_insts);
+  v.prm = reinterpret_cast<InstParams *>(base + o_prm);
+  v.res = reinterpret_cast<InstRes *>(base + o_res);
+  v.part = reinterpret_cast<double *>(base + o_part);
+  v.prows = prows;
+  v.ubuf = u_direct ? nullptr : base + o_u;
+  v.u_ext = u_direct ? U : nullptr;
+  v.Z0 = reinterpret_cast<double *>(base + o_z0);
+  v.TY = h.direct ? nullptr : reinterpret_cast<double *>(base + o_ty);
+  v.yp = h.direct ? nullptr : reinterpret_cast<double *>(base + o_yp);
+  v.Bpair = h.direct ? nullptr : reinterpret_cast<double *>(base + o_bp);
+  if (P.insts_dirty) {
+    // the handle's own descriptor must be on the device before it is copied
+    std::string e2;
+    if (upload_params(P, s, st, e2) != HALLAR_OK) {
+      err = e2;
+      return HALLAR_E_HIP;
+    }
+  }
+  op_noalloc_setup(st, P.d_insts, s, v);
+  const Tile *T_ = slot_tiles(P, s);
+  const int32_t *IL = slot_ilist(P, s);
+  const InstDev *D = v.insts;
+  if (!u_direct) op_pack_op(P.prec, R, st, T_, nt, D, U, r, ldu, RU);
+  op_lr_dots(P.prec, R, st, T_, nt, D, RU);
+  op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0, h.direct && h.m > 0 ? T + 1 : nullptr);
+  if (!h.direct) op_gen_constraints(P.prec, st, IL, 1, h.m, D, 1);
+  op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
+  HL_TRY(hipMemcpyAsync(T, &v.res->v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
+  if (h.m > 0 && !h.direct)
+    HL_TRY(hipMemcpyAsync(T + 1, v.TY, sizeof(double) * h.m, hipMemcpyDeviceToDevice, st), "T");
+  HL_TRY(hipGetLastError(), "eval launch");
+  return HALLAR_OK;
+}
+
 hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, int64_t ldu, void *W, int64_t ldw,
                          hipStream_t st) {
   Slot &S = *P.slots[s];

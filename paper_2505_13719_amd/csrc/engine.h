@@ -94,6 +94,7 @@ struct Pool {
   double *d_dl = nullptr, *h_dl = nullptr;
   int64_t dl_cap = 0;
   bool insts_dirty = true;
+  void *scratch = nullptr;  // device address of the allocation-free evaluation's scratch on this pool's device
   std::deque<std::pair<int64_t, hallar_result>> finished;
   int64_t rounds = 0;
   std::string err;
@@ -156,6 +157,7 @@ int pool_active(const Pool &P);
 
 // standalone operator calls on slot s of P
 hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st);
+hallar_status op_eval_AUUt_noalloc(Pool &P, int s, const void *U, int r, int64_t ldu, double *T, hipStream_t st);
 hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, int64_t ldu, void *W, int64_t ldw,
                          hipStream_t st);
 hallar_status op_min_eig(Pool &P, int s, const double *p, const double *v0, double tol, int max_iter, double *lambda,

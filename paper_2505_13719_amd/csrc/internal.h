@@ -154,4 +154,24 @@ struct InstDev {
   InstRes *res;
 };
 
+// Scratch of the allocation-free evaluation: one static device array per GPU.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Where the allocation-free evaluation puts what it writes (all inside the
+// scratch array): the descriptor array (instance s at insts[s]), parameters,
+// result scalars, partial sums (prows rows per slot), the packed U (unless
+// u_ext, the caller's U read in place), low-rank products and, in general
+// mode, T, y' and the per-pair dot products.
+struct NoallocViews {
+  InstDev *insts;
+  InstParams *prm;
+  InstRes *res;
+  double *part;
+  int32_t prows;
+  void *ubuf;
+  const void *u_ext;
+  double *Z0, *TY, *yp, *Bpair;
+};
+
 }  // namespace hl

@@ -10,6 +10,8 @@
 //   and the strictly-lower transpose with pair ids for the symmetric SpMM
 //   (Algorithm 4 uses the pattern S u S^T).
 // Everything here is memory bound: no MFMA (no dense contraction).
+#include <mutex>
+
 #include "internal.h"
 
 namespace hl {
@@ -2243,6 +2245,62 @@ void op_lz_scale(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
 }
 void op_lz_combine(hipStream_t s, const Tile *t, int nt, const InstDev *d, int to_lzv) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_combine, dim3(nt), dim3(BLOCK), 0, s, t, d, to_lzv);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation of A~(UU^T): its scratch (descriptor copy,
+// parameters, result scalars, partial sums, packed U, general-mode per-pair
+// and per-constraint vectors) lives in one file-scope device array per GPU,
+// held until the process ends.  Host code never passes the array's name to
+// a kernel: it takes the device address once per device from
+// hipGetSymbolAddress and uses that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void **ptr) {
+  static std::mutex mu;
+  static void *addr[NOALLOC_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = q;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+// One thread copies the handle's descriptor and parameters into the scratch
+// and points every buffer the evaluation writes at the scratch.
+__global__ void k_noalloc_setup(const InstDev *__restrict__ src, int s, NoallocViews v) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  InstDev I = src[s];
+  InstParams P = *I.prm;
+  P.beta = 0.0;
+  P.buf[RU] = v.u_ext ? NBUF : 0;
+  P.ext[0] = const_cast<void *>(v.u_ext);
+  I.prm = v.prm;
+  I.res = v.res;
+  I.part = v.part;
+  I.prows = v.prows;
+  I.buf[0] = v.ubuf;
+  I.Z0 = v.Z0;
+  if (!I.direct) {
+    I.TY = v.TY;
+    I.yp = v.yp;
+    I.Bpair = v.Bpair;
+  }
+  for (int q = 0; q < NRES; ++q) v.res->v[q] = 0.0;
+  *v.prm = P;
+  v.insts[s] = I;
+}
+void op_noalloc_setup(hipStream_t st, const InstDev *src, int s, const NoallocViews &v) {
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(64), 0, st, src, s, v);
 }
 
 }  // namespace hl

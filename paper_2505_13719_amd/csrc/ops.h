@@ -52,4 +52,11 @@ void op_lz_update(hipStream_t s, const Tile *t, int nt, const InstDev *d, int fi
 void op_lz_scale(hipStream_t s, const Tile *t, int nt, const InstDev *d);
 void op_lz_combine(hipStream_t s, const Tile *t, int nt, const InstDev *d, int to_lzv);
 
+// Allocation-free evaluation (hallar_eval_AUUt_noalloc): the scratch array's
+// device address on the current device (resolved once per device), and the
+// kernel that copies instance s's descriptor into it with every buffer the
+// evaluation writes pointed into the scratch.
+hipError_t noalloc_scratch(void **ptr);
+void op_noalloc_setup(hipStream_t st, const InstDev *src, int s, const NoallocViews &v);
+
 }  // namespace hl

@@ -66,7 +66,7 @@ class hallar_eig_info(C.Structure):
 
 
 EXPORTS = ["hallar_default_options", "hallar_create", "hallar_destroy", "hallar_last_error", "hallar_describe",
-           "hallar_eval_AUUt", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
+           "hallar_eval_AUUt", "hallar_eval_AUUt_noalloc", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
            "hallar_solve_batch", "hallar_footprint", "hallar_pool_create", "hallar_pool_destroy",
            "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage", "hallar_profile",
            "hallar_pool_profile", "hallar_schedule", "hallar_inspect"]
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.hallar_describe.argtypes = [vp, i64p, i64p, i64p]
     L.hallar_schedule.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), i64p]
     L.hallar_eval_AUUt.argtypes = [vp, vp, C.c_int32, C.c_int64, vp, vp]
+    L.hallar_eval_AUUt_noalloc.argtypes = [vp, vp, C.c_int32, C.c_int64, vp, vp]
     L.hallar_adjoint_spmm.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, vp, C.c_int64, vp]
     L.hallar_min_eig.argtypes = [vp, vp, vp, C.c_double, C.c_int32, f64p, vp, C.POINTER(hallar_eig_info), vp]
     L.hallar_solve.argtypes = [vp, vp, C.c_int32, vp, C.POINTER(hallar_result)]
@@ -240,6 +241,15 @@ def hallar_eval_AUUt(h, U, T, stream=None):
     _need(T, "T", torch.float64, numel=h.m + 1)
     r = U.shape[1]
     return _check(load().hallar_eval_AUUt(h, _ptr(U), r, U.stride(0), _ptr(T), _stream(stream)), h)
+
+
+def hallar_eval_AUUt_noalloc(h, U, T, stream=None):
+    """As hallar_eval_AUUt, with the library's static per-GPU scratch array
+    instead of the handle's workspace (no allocation at call time)."""
+    import torch
+    _need(U, "U", _optype(h), rows=h.n)
+    _need(T, "T", torch.float64, numel=h.m + 1)
+    return _check(load().hallar_eval_AUUt_noalloc(h, _ptr(U), U.shape[1], U.stride(0), _ptr(T), _stream(stream)), h)
 
 
 def hallar_adjoint_spmm(h, p, U, W, stream=None):
