@@ -1,0 +1,100 @@
+"""Summaries of rocprofv3 output for the kernels of this library.
+
+    python -m paper_2505_13719_amd.profiling trace <kernel_trace.csv>
+    python -m paper_2505_13719_amd.profiling counters <fetch counter_collection.csv> <write counter_collection.csv>
+        [--copy-kib KIB]
+
+`trace` prints, per kernel name, the dispatch count, average and total
+duration and share of the traced kernel time (from rocprofv3
+--kernel-trace CSV).  `counters` prints, per kernel, the average FETCH_SIZE
+and WRITE_SIZE per dispatch (KiB, from two --pmc passes) and the HBM bytes
+per launch after scaling each counter by what it reads for a plain device
+copy of known size (the largest torch copy kernel in the same run moves
+--copy-kib KiB each way, 1 GiB by default), plus one machine-readable line
+per kernel: traffic_bytes_per_launch[<kernel>] = <bytes> dispatches=<n>.
+"""
+import csv
+import sys
+from collections import defaultdict
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(names)
+
+
+def trace(path):
+    by = defaultdict(list)
+    for r in _rows(path):
+        name = _col(r, "Kernel_Name", "KernelName", "Name")
+        t0 = int(_col(r, "Start_Timestamp", "BeginNs", "Start"))
+        t1 = int(_col(r, "End_Timestamp", "EndNs", "End"))
+        by[name].append((t1 - t0) * 1e-3)
+    total = sum(sum(v) for v in by.values())
+    print("| kernel | calls | avg us | total ms | % |")
+    print("|---|---:|---:|---:|---:|")
+    for name, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{name}` | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) * 1e-3:.1f} | {100 * sum(v) / total:.2f} |")
+
+
+def _counter(path, cname):
+    acc = defaultdict(lambda: [0.0, 0])
+    for r in _rows(path):
+        if _col(r, "Counter_Name", "CounterName") != cname:
+            continue
+        name = _col(r, "Kernel_Name", "KernelName")
+        acc[name][0] += float(_col(r, "Counter_Value", "CounterValue"))
+        acc[name][1] += 1
+    return {k: (s / n, n) for k, (s, n) in acc.items()}
+
+
+def _max_copy(path, cname):
+    """Largest single dispatch of a runtime copy kernel (the calibration
+    copy: the bench's 1 GiB device-to-device copy)."""
+    best, name = 0.0, None
+    for r in _rows(path):
+        k = _col(r, "Kernel_Name", "KernelName")
+        if _col(r, "Counter_Name", "CounterName") == cname and "hl::" not in k and "copy" in k.lower():
+            v = float(_col(r, "Counter_Value", "CounterValue"))
+            if v > best:
+                best, name = v, k
+    return best, name
+
+
+def counters(fetch_path, write_path, copy_kib=1 << 20):
+    fe = _counter(fetch_path, "FETCH_SIZE")
+    wr = _counter(write_path, "WRITE_SIZE")
+    cf, cal = _max_copy(fetch_path, "FETCH_SIZE")
+    cw, _ = _max_copy(write_path, "WRITE_SIZE")
+    fs = copy_kib / cf if cf > 0 else 1.0
+    ws = copy_kib / cw if cw > 0 else 1.0
+    print(f"Calibration: the largest `{cal}` dispatch (a {copy_kib} KiB device copy) reads FETCH_SIZE = "
+          f"{cf:.0f} KiB and WRITE_SIZE = {cw:.0f} KiB: FETCH_SIZE scaled by {fs:.4f}, WRITE_SIZE by {ws:.4f}.\n"
+          if cal else "No copy dispatch found: counters unscaled.\n")
+    print("| kernel | dispatches | FETCH KiB | WRITE KiB | HBM MB / launch (scaled) |")
+    print("|---|---:|---:|---:|---:|")
+    lines = []
+    for name, (f, n) in sorted(fe.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        w = wr.get(name, (0.0, 0))[0]
+        b = (f * fs + w * ws) * 1024
+        print(f"| `{name}` | {n} | {f:.0f} | {w:.0f} | {b / 1e6:.1f} |")
+        lines.append(f"traffic_bytes_per_launch[{name}] = {b:.0f} dispatches={n}")
+    print()
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2])
+    else:
+        kib = 1 << 20
+        if "--copy-kib" in sys.argv:
+            kib = int(sys.argv[sys.argv.index("--copy-kib") + 1])
+        counters(sys.argv[2], sys.argv[3], kib)
