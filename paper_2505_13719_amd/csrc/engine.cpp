@@ -1734,6 +1734,16 @@ void slot_start_solve(Pool &P, int s) {
   Slot &S = *P.slots[s];
   S.done = false;
   S.result = hallar_result{};
+  // a solve starts from the instance alone: nothing a previous solve or
+  // operator call on this slot left in the parameters (the Lanczos shift in
+  // particular, which changes the rounding of every eigen solve) carries over
+  {
+    const double tau = S.prm.tau, tau2 = S.prm.tau2;
+    S.prm = InstParams{};
+    S.prm.tau = tau;
+    S.prm.tau2 = tau2;
+  }
+  S.lz_sigma = 0.0;
   S.free_bufs.clear();
   for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);
   if (S.task) delete S.task;
@@ -1766,10 +1776,12 @@ hallar_status pool_run(Pool &P, int max_rounds) {
 }
 
 // ------------------------------------------------------------------ standalone operator calls
-static hallar_status upload_params(Pool &P, int s, hipStream_t st, std::string &err) {
-  // pinned source; the standalone calls always write the same role table
-  P.h_prm[s] = P.slots[s]->prm;
-  HL_TRY(hipMemcpyAsync(P.d_prm + s, P.h_prm + s, sizeof(InstParams), hipMemcpyHostToDevice, st), "params");
+// The standalone calls' parameters go down as a kernel argument (copied at
+// enqueue time): consecutive asynchronous calls with different role tables
+// cannot see each other's values, and the slot's own parameters are left as
+// the solver set them.
+static hallar_status upload_params(Pool &P, int s, const InstParams &prm, hipStream_t st, std::string &err) {
+  op_put_params(st, P.d_prm + s, prm);
   if (P.insts_dirty) {
     HL_TRY(hipMemcpyAsync(P.d_insts, P.h_insts.data(), sizeof(InstDev) * P.max_slots, hipMemcpyHostToDevice, st),
            "descriptors");
@@ -1807,10 +1819,11 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
   }
   // the caller's U is read in place when its rows are the bucket's rows
   const bool u_direct = in_place(U, r, ldu, R);
-  S.prm.buf[RU] = u_direct ? NBUF : 0;
-  S.prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
-  S.prm.beta = 0.0;
-  if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
+  InstParams prm = S.prm;
+  prm.buf[RU] = u_direct ? NBUF : 0;
+  prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
+  prm.beta = 0.0;
+  if (upload_params(P, s, prm, st, err) != HALLAR_OK) return HALLAR_E_HIP;
   const Tile *T_ = slot_tiles(P, s);
   const int nt = (int)S.hp.tiles.size();
   const int32_t *IL = slot_ilist(P, s);
@@ -1889,7 +1902,7 @@ hallar_status op_eval_AUUt_noalloc(Pool &P, int s, const void *U, int r, int64_t
   if (P.insts_dirty) {
     // the handle's own descriptor must be on the device before it is copied
     std::string e2;
-    if (upload_params(P, s, st, e2) != HALLAR_OK) {
+    if (upload_params(P, s, S.prm, st, e2) != HALLAR_OK) {
       err = e2;
       return HALLAR_E_HIP;
     }
@@ -1926,11 +1939,12 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
   const uintptr_t u0 = reinterpret_cast<uintptr_t>(U), w0 = reinterpret_cast<uintptr_t>(W);
   const bool overlap = u0 < w0 + (size_t)S.hp.n * ldw * esz && w0 < u0 + (size_t)S.hp.n * ldu * esz;
   const bool w_direct = in_place(W, r, ldw, R) && !overlap;
-  S.prm.buf[RU] = u_direct ? NBUF : 0;
-  S.prm.buf[RU2] = w_direct ? NBUF + 1 : 1;
-  S.prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
-  S.prm.ext[1] = w_direct ? W : nullptr;
-  if (upload_params(P, s, st, err) != HALLAR_OK) return HALLAR_E_HIP;
+  InstParams prm = S.prm;
+  prm.buf[RU] = u_direct ? NBUF : 0;
+  prm.buf[RU2] = w_direct ? NBUF + 1 : 1;
+  prm.ext[0] = u_direct ? const_cast<void *>(U) : nullptr;
+  prm.ext[1] = w_direct ? W : nullptr;
+  if (upload_params(P, s, prm, st, err) != HALLAR_OK) return HALLAR_E_HIP;
   const Tile *T_ = slot_tiles(P, s);
   const int nt = (int)S.hp.tiles.size();
   const int32_t *IL = slot_ilist(P, s);
@@ -1964,6 +1978,10 @@ hallar_status op_min_eig(Pool &P, int s, const double *p, const double *v0, doub
   hallar_options o2 = P.opts;
   o2.eig_tol = tol;
   S.done = false;
+  // the same call gives the same result: the start vector's seed and the
+  // SpMV shift do not depend on earlier calls
+  S.result.n_eig_calls = 0;
+  S.lz_sigma = 0.0;
   if (S.task) delete S.task;
   S.free_bufs.clear();
   for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);

@@ -2228,6 +2228,15 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   else if (op == RD_GRAM) ny = (R * R + 63) / 64;
   hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
+// Parameters of a standalone operator call, passed by value as the kernel's
+// argument (captured when the launch is enqueued, so nothing host-side has to
+// stay unchanged until the stream reaches it).
+__global__ void k_put_params(InstParams *dst, InstParams v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v) {
+  hipLaunchKernelGGL(k_put_params, dim3(1), dim3(64), 0, s, dst, v);
+}
 void op_lz_start(hipStream_t s, const Tile *t, int nt, const InstDev *d) {
   if (nt > 0) hipLaunchKernelGGL(k_lz_start, dim3(nt), dim3(BLOCK), 0, s, t, d);
 }

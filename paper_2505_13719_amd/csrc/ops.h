@@ -13,6 +13,7 @@ enum RedOpH : int {
   RDH_LZ_CHECKH2, RDH_TRIAL_FUSED, RDH_YP_PROJ
 };
 
+void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v);
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp,
               double *tout = nullptr);
 void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);

@@ -179,3 +179,44 @@ def test_in_place_matches_packed(prec, r):
         assert normwise(out[0][0].numpy(), oracle.a_tilde(prob, Uo), abs_terms_T(prob, Uo)) <= TOL[prec]
     finally:
         H.hallar_destroy(h)
+
+
+def test_async_calls_keep_their_parameters():
+    """Back-to-back asynchronous calls with different inputs and role tables
+    (in place and packed, eval and adjoint) each see their own parameters:
+    the results equal the same calls made one at a time with a sync between
+    them, bit for bit; an eigen solve on the same handle afterwards runs."""
+    d = dev()
+    prob = si.mc_planted(700, 900, 3, 60000, seed=3)
+    rng = np.random.default_rng(4)
+    h = H.hallar_create(prob, H.FP64)
+    try:
+        U1 = torch.tensor(rng.standard_normal((prob.n, 4)), device=d)                 # in place
+        U2 = torch.tensor(rng.standard_normal((prob.n, 3)), device=d)                 # packed
+        U3 = torch.tensor(rng.standard_normal((prob.n, 8)), device=d)                 # in place, wider
+        p = torch.tensor(rng.standard_normal(prob.m), device=d)
+
+        def calls(sync):
+            out = []
+            for U in (U1, U2, U3):
+                T = torch.empty(prob.m + 1, dtype=torch.float64, device=d)
+                H.hallar_eval_AUUt(h, U, T)
+                if sync:
+                    torch.cuda.synchronize()
+                W = torch.empty_like(U)
+                H.hallar_adjoint_spmm(h, p, U, W)
+                if sync:
+                    torch.cuda.synchronize()
+                out.append((T, W))
+            torch.cuda.synchronize()
+            return [(T.cpu(), W.cpu()) for T, W in out]
+
+        ref = calls(True)
+        got = calls(False)
+        for (Tr, Wr), (Tg, Wg) in zip(ref, got):
+            assert torch.equal(Tr, Tg) and torch.equal(Wr, Wg)
+        v = torch.empty(prob.n, dtype=torch.float64, device=d)
+        lam, info = H.hallar_min_eig(h, p * 1e-3, v, tol=1e-9, max_iter=2000)
+        assert np.isfinite(lam)
+    finally:
+        H.hallar_destroy(h)

@@ -272,3 +272,35 @@ def test_profile_levels():
         else:
             assert v["launches"] == 0, k
     assert out[0][0]["pval"] == out[1][0]["pval"] == out[2][0]["pval"]
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
+def test_repeated_solves_identical(prec):
+    """A solve depends on the instance, U0 and the options only: repeated
+    solves on one handle, with an eigen solve on other multipliers in
+    between, give the same bits (nothing of an earlier solve or call, such as
+    the last Lanczos shift, carries over); repeated eigen solves agree too."""
+    d = dev()
+    rng = np.random.default_rng(3)
+    i, j = si.er_edges(500, 8.0 / 499, rng)
+    prob = si.maxcut_problem(500, i, j, si.pm1_weights(i.size, rng))
+    h = H.hallar_create(prob, prec, H.options(eps=1e-5))
+    try:
+        U0 = torch.tensor(si.gaussian_u0(prob.n, 7), device=d)
+        out = []
+        for k in range(3):
+            res = H.hallar_solve(h, U0)
+            U = torch.empty((prob.n, res["rank"]), dtype=torch.float64, device=d)
+            H.hallar_get_solution(h, U, None)
+            out.append((res, U.cpu()))
+            if k == 0:
+                v = torch.empty(prob.n, dtype=torch.float64, device=d)
+                p = torch.tensor(rng.standard_normal(prob.m), device=d)
+                lams = [H.hallar_min_eig(h, p, v, tol=1e-9, max_iter=40)[0] for _ in range(2)]
+                assert lams[0] == lams[1]
+        for res, U in out[1:]:
+            for k in ("status", "pval", "dval", "gap", "rank", "n_fista_trials", "n_matvec", "n_rounds"):
+                assert res[k] == out[0][0][k], (k, res[k], out[0][0][k])
+            assert torch.equal(U, out[0][1])
+    finally:
+        H.hallar_destroy(h)
