@@ -67,8 +67,13 @@ typedef enum { HALLAR_FP64 = 0, HALLAR_FP32_MIXED = 1 } hallar_precision;
  * (row, col, con) triples are summed.  Low-rank part: n_lowrank terms; term t
  * adds K_t D_t K_t^T to A_{lr_con[t]}, K_t is n x lr_rank[t] row-major at
  * K + K_off[t], D_t is lr_rank[t] x lr_rank[t] row-major at D + D_off[t].
- * The library supports low-rank terms on the objective only (lr_con = 0,
- * at most one term, rank <= 2); others give HALLAR_E_UNSUPPORTED. */
+ * Supported: on the objective (lr_con = 0) at most one term of rank <= 2;
+ * on the constraints any number of terms of any rank, at most 4096 columns
+ * in all (the terms of one constraint are merged); others give
+ * HALLAR_E_UNSUPPORTED.  A constraint with a low-rank part is summed per
+ * constraint (the general mode of the index lists L_ij), and its low-rank
+ * part enters A~(UU^T) as Tr(D (K^T U)(K^T U)^T) (Algorithm 3) and the
+ * adjoint as K (D (K^T U)) (Algorithm 5), K^T U a dense contraction. */
 typedef struct {
   int64_t n;             /* X is n x n, 1 <= n < 2^31 */
   int64_t m;             /* number of constraints A_1..A_m, 0 <= m < 2^31 */

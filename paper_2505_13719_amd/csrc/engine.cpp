@@ -162,6 +162,7 @@ struct Layout {
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, m64_low, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
       ilist;
+  size_t Kc, Kc64, Dc, lc_con, lc_off, lc_doff, lc_of_con, lc_part, lc_Y, lc_Z, lc_T, lc_v, lc_zv, lc_Tv;
   size_t total;
 };
 
@@ -223,6 +224,23 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
   L.gram = c.take(nt * (size_t)Rcap * Rcap * 8);
   L.tiles = c.take(nt * sizeof(Tile));
   L.ilist = c.take(sizeof(int32_t));
+  if (hp.rk > 0) {
+    const size_t rk = hp.rk, nlc = hp.nlc;
+    L.Kc = c.take(n * rk * sz);
+    L.Kc64 = prec == 0 ? L.Kc : c.take(n * rk * 8);
+    L.Dc = c.take(hp.Dc.size() * 8);
+    L.lc_con = c.take(nlc * 4);
+    L.lc_off = c.take((nlc + 1) * 4);
+    L.lc_doff = c.take(nlc * 4);
+    L.lc_of_con = c.take(m * 4);
+    L.lc_part = c.take(nt * rk * R_MAX * 8);
+    L.lc_Y = c.take(rk * R_MAX * 8);
+    L.lc_Z = c.take(2 * rk * R_MAX * 8);
+    L.lc_T = c.take(nlc * 8);
+    L.lc_v = c.take(rk * 8);
+    L.lc_zv = c.take(rk * 8);
+    L.lc_Tv = c.take(nlc * 8);
+  }
   L.total = c.off;
   return L;
 }
@@ -400,6 +418,17 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     put(base, L.cent, h.cent, st);
     put(base, L.epair, h.epair, st);
   }
+  if (h.rk > 0) {
+    conv(h.Kc, L.Kc);
+    if (f32) put(base, L.Kc64, h.Kc, st);
+    put(base, L.Dc, h.Dc, st);
+    put(base, L.lc_con, h.lc_con, st);
+    put(base, L.lc_off, h.lc_off, st);
+    put(base, L.lc_doff, h.lc_doff, st);
+    put(base, L.lc_of_con, h.lc_of_con, st);
+    (void)hipMemsetAsync(base + L.lc_Z, 0, 2 * (size_t)h.rk * R_MAX * 8, st);
+    (void)hipMemsetAsync(base + L.lc_zv, 0, (size_t)h.rk * 8, st);
+  }
   put(base, L.tiles, h.tiles, st);
   std::vector<int32_t> il{s};
   put(base, L.ilist, il, st);
@@ -480,6 +509,24 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   D.gram = (double *)at(L.gram);
   D.prm = P.d_prm + s;
   D.res = P.d_res + s;
+  D.rk = h.rk;
+  D.nlc = h.nlc;
+  if (h.rk > 0) {
+    D.Kc = at(L.Kc);
+    D.Kc64 = (const double *)at(L.Kc64);
+    D.Dc = (const double *)at(L.Dc);
+    D.lc_con = (const int32_t *)at(L.lc_con);
+    D.lc_off = (const int32_t *)at(L.lc_off);
+    D.lc_doff = (const int32_t *)at(L.lc_doff);
+    D.lc_of_con = (const int32_t *)at(L.lc_of_con);
+    D.lc_part = (double *)at(L.lc_part);
+    D.lc_Y = (double *)at(L.lc_Y);
+    D.lc_Z = (double *)at(L.lc_Z);
+    D.lc_T = (double *)at(L.lc_T);
+    D.lc_v = (double *)at(L.lc_v);
+    D.lc_zv = (double *)at(L.lc_zv);
+    D.lc_Tv = (double *)at(L.lc_Tv);
+  }
   S.dev = D;
   S.used = true;
   S.free_bufs.clear();
@@ -638,6 +685,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   bool any_lr = false;
   int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
   int64_t max_nl = 0, nrows = 0;
+  int max_rk = 0;  // columns of the constraints' low-rank parts
   // the trial's SDDMM and gradient SpMM run as one kernel when every instance
   // recomputes its lower half, has no low-rank objective term (its product
   // is reduced between the two) and the rows are narrow
@@ -652,6 +700,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     if (h.low_recompute) max_pb = std::max<int64_t>(max_pb, h.nlower);
     max_nl = std::max<int64_t>(max_nl, h.nlower);
     nrows += h.n;
+    max_rk = std::max(max_rk, h.rk);
   }
   // the trial's reduces are split over several workgroups for instances with
   // thousands of tiles (one workgroup then waits on its own loads); each
@@ -670,7 +719,14 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       if (any_lr) op_lr_dots(prec, R, st, T, nt, D, xrole);
       op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
       if (gni > 0) {
+        if (max_rk > 0) {
+          // the constraints' low-rank parts of T (Algorithm 3) before the AL
+          // epilogue of each constraint, their SpMM coefficients after it
+          op_lc_kty(prec, R, st, T, nt, D, max_rk, xrole, 0);
+          op_lc_red(st, GL, gni, D, LC_Y_T, R, zsel);
+        }
         op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
+        if (max_rk > 0) op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
         if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
       }
     }
@@ -768,6 +824,11 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
             }
           }
         const double vb = vsweep + wbytes;
+        if (max_rk > 0) {
+          // K^T v_j and its coefficients for the SpMV's low-rank parts
+          op_lc_kty(prec, R, st, T, nt, D, max_rk, 0, 1);
+          op_lc_red(st, IL, ni, D, LC_V_LZ, 1, 0);
+        }
         {
           // SpMV fused with the first Gram-Schmidt dots
           ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv + vsweep, st);
@@ -798,6 +859,10 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       {
         ProfScope ps(P, KC_OTHER, 0.0, st);
         op_fw_den(st, T, nt, D);
+        if (gni > 0 && max_rk > 0) {
+          op_lc_kty(prec, R, st, T, nt, D, max_rk, 0, 2);
+          op_lc_red(st, GL, gni, D, LC_V_FW, 1, 0);
+        }
         if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
       }
       red(RDH_FW_DEN, 0);
@@ -1834,6 +1899,10 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
   op_lr_dots(P.prec, R, st, T_, nt, D, RU);
   // direct mode: each constrained pair's lane writes T_l into the caller's T
   op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0, S.hp.direct && S.hp.m > 0 ? T + 1 : nullptr);
+  if (S.hp.rk > 0) {
+    op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
+    op_lc_red(st, IL, 1, D, LC_Y_T, R, 0);
+  }
   if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);
   op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
   HL_TRY(hipMemcpyAsync(T, &P.d_res[s].v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
@@ -1861,6 +1930,10 @@ hallar_status op_eval_AUUt_noalloc(Pool &P, int s, const void *U, int r, int64_t
     return HALLAR_E_HIP;
   }
   const HostProblem &h = S.hp;
+  if (h.rk > 0) {
+    err = "the allocation-free evaluation does not take low-rank constraint terms";
+    return HALLAR_E_UNSUPPORTED;
+  }
   const bool u_direct = in_place(U, r, ldu, R);
   const int nt = (int)h.tiles.size();
   const int prows = (int)prows_for(h);
@@ -1954,6 +2027,11 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
   if (S.hp.r0 > 0) {
     op_lr_dots(P.prec, R, st, T_, nt, D, RU);
     op_reduce(st, IL, 1, D, RDH_LRONLY, 0, R, 0);
+  }
+  if (S.hp.rk > 0) {
+    // blockdiag(p_l D_l) K^T U for the constraints' low-rank parts (Algorithm 5)
+    op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
+    op_lc_red(st, IL, 1, D, LC_Y_Z, R, 0, p);
   }
   op_spmm(P.prec, R, st, T_, nt, D, RU, 0, 0, RU2, SPM_PLAIN);
   if (!w_direct) op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);

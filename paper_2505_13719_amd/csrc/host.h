@@ -42,6 +42,11 @@ struct HostProblem {
   // low-rank objective
   int32_t r0 = 0;
   std::vector<double> K0, D0;
+  // low-rank parts of the constraints: terms merged per constraint (their K
+  // columns side by side, their D blocks on the diagonal), K row-major n x rk
+  int32_t rk = 0, nlc = 0;
+  std::vector<double> Kc, Dc;
+  std::vector<int32_t> lc_con, lc_off, lc_doff, lc_of_con;
   std::vector<double> b;
   double b_l1 = 0.0, c_l1 = 0.0;
   // tiles (row ranges) and their pair-stream choices; the schedule's two

@@ -18,6 +18,7 @@ constexpr int BLOCK = 256;       // threads per workgroup (4 wave64)
 constexpr int RBLOCK = 1024;     // threads of a reduce workgroup (16 wave64)
 constexpr int LR_MAX = 2;        // rank of the low-rank objective term
 constexpr int R_MAX = 64;        // columns of U
+constexpr int RK_MAX = 4096;     // columns of the constraints' low-rank parts (all terms together)
 constexpr int KMAX = 64;         // Lanczos basis vectors before a restart
 constexpr int PSTRIDE = 144;     // partial-sum slots per tile (>= KMAX + 1 + LR_MAX, >= 3 + LR_MAX * R_MAX)
 constexpr int LZ_W2_SLOT = PSTRIDE - 1;  // partial ||G v_j||^2 of the Lanczos SpMV
@@ -152,7 +153,28 @@ struct InstDev {
   double *gram;                             // (R x R) x ntiles Gram partials, entry-major
   InstParams *prm;
   InstRes *res;
+  // low-rank parts of the constraints (Section 3.2, eq. HSLR-rep-body): rk
+  // columns K (n x rk row-major, operator type, and an FP64 copy for the
+  // Lanczos SpMV), nlc terms, one per constraint that has one: term q sits on
+  // constraint lc_con[q] (1..m), owns columns lc_off[q]..lc_off[q+1] and the
+  // D block at Dc + lc_doff[q]; lc_of_con[l - 1] is constraint l's term or -1
+  int32_t rk, nlc;
+  const void *Kc;
+  const double *Kc64, *Dc;
+  const int32_t *lc_con, *lc_off, *lc_doff, *lc_of_con;
+  double *lc_part;   // per tile: rk x R_MAX partial sums of K^T X (or K^T v)
+  double *lc_Y;      // K^T X, rk x R_MAX
+  double *lc_Z;      // 2 slots (zsel) of blockdiag(y'_l D_q) K^T X, rk x R_MAX each
+  double *lc_T;      // nlc: Tr(D_q (K_q^T X)(K_q^T X)^T), the low-rank part of A_l . X X^T
+  double *lc_v;      // rk: K^T v for a vector v
+  double *lc_zv;     // rk: blockdiag(y''_l D_q) K^T v (added by the Lanczos SpMV)
+  double *lc_Tv;     // nlc: (K_q^T v)^T D_q (K_q^T v) (Frank-Wolfe step size)
 };
+
+// Reductions of the constraints' low-rank parts (k_lc_red): Y = K^T X and
+// lc_T; lc_Z from the Y in place with the multipliers (I.yp or given); Y
+// then lc_Z; K^T v then lc_zv (Lanczos, multipliers I.yp); K^T v then lc_Tv.
+enum LcMode : int { LC_Y_T = 0, LC_Z, LC_Y_Z, LC_V_LZ, LC_V_FW };
 
 // Scratch of the allocation-free evaluation: one static device array per GPU.
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;

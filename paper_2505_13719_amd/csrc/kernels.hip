@@ -444,6 +444,10 @@ __global__ __launch_bounds__(BLOCK) void k_gen_constraints(const int32_t *__rest
       const int id = I.cent[e];
       t += I.ew64[id] * I.Bpair[I.epair[id]];  // (2 - delta_ij) (A_l)_ij <U_i, U_j>
     }
+    if (I.nlc > 0) {
+      const int q = I.lc_of_con[l];
+      if (q >= 0) t += I.lc_T[q];  // + K_l D_l K_l^T . U U^T (Algorithm 3)
+    }
     const double r = t - I.b[l];
     const double y = I.p[l] + P.beta * r;
     acc[0] = I.p[l] * r;
@@ -606,6 +610,17 @@ __device__ __forceinline__ void spmm_epi_apply(const InstDev &I, const InstParam
     const double kv = (double)K0[(size_t)i * r0 + t];
 #pragma unroll
     for (int e = 0; e < NC; ++e) w[e] += kv * Z0[t * R_MAX + ch * NC + e];
+  }
+  if (I.rk > 0) {
+    // constraints' low-rank parts: + K_i . (blockdiag(y_l D_l) K^T X) (Algorithm 5)
+    const int rk = I.rk;
+    const T *__restrict__ Kc = reinterpret_cast<const T *>(I.Kc) + (size_t)i * rk;
+    const double *__restrict__ Zc = I.lc_Z + (size_t)a.zsel * rk * R_MAX + ch * NC;
+    for (int k = 0; k < rk; ++k) {
+      const double kv = (double)Kc[k];
+#pragma unroll
+      for (int e = 0; e < NC; ++e) w[e] += kv * Zc[(size_t)k * R_MAX + e];
+    }
   }
   const size_t off = (size_t)i * R + ch * NC;
   if (MODE == SP_PLAIN) {
@@ -1311,6 +1326,10 @@ __global__ __launch_bounds__(BLOCK) void k_fw_den_gen(const int32_t *__restrict_
       const int id = I.cent[e];
       t += I.ew64[id] * I.Bpair[I.epair[id]];
     }
+    if (I.nlc > 0) {
+      const int q = I.lc_of_con[l];
+      if (q >= 0) t += I.lc_Tv[q];
+    }
     I.Ty[l] = t;
     const double d = I.TY[l] - P.tau2 * t;
     acc[0] = d * d;
@@ -1473,6 +1492,10 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
     for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
+      if (I.rk > 0) {
+        const double *Kc = I.Kc64 + (size_t)i * I.rk;
+        for (int k = 0; k < I.rk; ++k) w += Kc[k] * I.lc_zv[k];
+      }
       // shifted three-term form: the Gram-Schmidt dots then see only the
       // small remainder, so the DGKS test can skip the second pass (the
       // host adds the shift and beta back into the projected matrix)
@@ -2228,11 +2251,168 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   else if (op == RD_GRAM) ny = (R * R + 63) / 64;
   hipLaunchKernelGGL(k_reduce, dim3(ni, ny), dim3(RBLOCK), 0, s, ilist, d, a);
 }
+// ---------------------------------------------------------------------------
+// Low-rank parts of the constraints (Section 3.2, eq. HSLR-rep-body;
+// Algorithm 3 for A~(XX^T) and Algorithm 5 for the adjoint): the dense
+// contraction K^T X over the rows of each tile, its fixed-order sum per
+// instance, then per term Tr(D_q Y_q Y_q^T), or the coefficients
+// blockdiag(y_l D_q) K^T X that the SpMM epilogue multiplies by K's rows.
+// ---------------------------------------------------------------------------
+// Per tile and group of 64 columns of K: partial K^T X (vsrc 0: the factor
+// of role xrole, R columns) or K^T v (vsrc 1: the Lanczos vector being
+// multiplied; 2: the Ritz vector lzv), into lc_part[tile][k][c].
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_lc_kty(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                  int32_t xrole, int32_t vsrc) {
+  constexpr int NC = NCh<T>::N;
+  constexpr int R = G * NC;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const int rk = I.rk;
+  if (rk == 0 || (int)blockIdx.y * 64 >= rk) return;  // uniform per block
+  const InstParams &P = *I.prm;
+  if (vsrc == 1 && P.lz_steps <= 0) return;
+  const int k = blockIdx.y * 64 + (threadIdx.x & 63), cq = threadIdx.x >> 6;
+  if (k >= rk) return;
+  double *out = I.lc_part + ((size_t)tl.lt * rk + k) * R_MAX;
+  if (vsrc == 0) {
+    const T *__restrict__ X = role_ptr<T>(I, P, xrole);
+    const T *__restrict__ K = reinterpret_cast<const T *>(I.Kc);
+    constexpr int PER = (R + 3) / 4;
+    double acc[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+    for (int i = tl.row0; i < tl.row1; ++i) {
+      const double kv = (double)K[(size_t)i * rk + k];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int c = cq + 4 * u;
+        if (c < R) acc[u] += kv * (double)X[(size_t)i * R + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int c = cq + 4 * u;
+      if (c < R) out[c] = acc[u];
+    }
+  } else {
+    if (cq != 0) return;
+    const double *v = vsrc == 1 ? lz_basis(I, P) + (size_t)P.lz_j * I.n : I.lzv;
+    double acc = 0.0;
+    for (int i = tl.row0; i < tl.row1; ++i) acc += I.Kc64[(size_t)i * rk + k] * v[i];
+    out[0] = acc;
+  }
+}
+
+// term of column k: lc_off[q] <= k < lc_off[q + 1]
+__device__ __forceinline__ int lc_term_of(const InstDev &I, int k) {
+  int lo = 0, hi = I.nlc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (I.lc_off[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// sum_ab D_q[a][b] <Y_a, Y_b> over c < R for term q (Y rows of stride ld)
+__device__ double lc_quad(const InstDev &I, int q, const double *Y, int ld, int R, int a0, int astep) {
+  const int o = I.lc_off[q], rl = I.lc_off[q + 1] - o;
+  const double *Dq = I.Dc + I.lc_doff[q];
+  double s = 0.0;
+  for (int a = a0; a < rl; a += astep)
+    for (int c = 0; c < R; ++c) {
+      double dy = 0.0;
+      for (int b = 0; b < rl; ++b) dy += Dq[(size_t)a * rl + b] * Y[(size_t)(o + b) * ld + c];
+      s += Y[(size_t)(o + a) * ld + c] * dy;
+    }
+  return s;
+}
+
+struct LcArgs {
+  int32_t mode;   // LcMode
+  int32_t R;      // columns of X
+  int32_t zsel;   // lc_Z slot
+  const double *mult;  // multipliers y_l of the coefficients (null: I.yp)
+};
+
+// One 1024-thread block per instance: the fixed-order sum of the tiles'
+// partials, then the mode's products.
+__global__ __launch_bounds__(RBLOCK) void k_lc_red(const int32_t *__restrict__ ilist, const InstDev *__restrict__ insts,
+                                                   LcArgs a) {
+  const InstDev &I = insts[ilist[blockIdx.x]];
+  const int rk = I.rk;
+  if (rk == 0) return;
+  const InstParams &P = *I.prm;
+  if (a.mode == LC_V_LZ && P.lz_steps <= 0) return;
+  const bool vec = a.mode == LC_V_LZ || a.mode == LC_V_FW;
+  const int R = vec ? 1 : a.R, ld = vec ? 1 : R_MAX, nt = I.ntiles;
+  double *Y = vec ? I.lc_v : I.lc_Y;
+  if (a.mode != LC_Z) {
+    for (int q = threadIdx.x; q < rk * R; q += blockDim.x) {
+      const int k = q / R, c = q - (q / R) * R;
+      double s = 0.0;
+      for (int t = 0; t < nt; ++t) s += I.lc_part[((size_t)t * rk + k) * R_MAX + c];
+      Y[(size_t)k * ld + c] = s;
+    }
+    __syncthreads();
+  }
+  if (a.mode == LC_Y_T || a.mode == LC_V_FW) {
+    double *out = a.mode == LC_Y_T ? I.lc_T : I.lc_Tv;
+    // small terms: one thread each; larger ones: the whole block, in turn
+    for (int q = threadIdx.x; q < I.nlc; q += blockDim.x)
+      if (I.lc_off[q + 1] - I.lc_off[q] <= 8) out[q] = lc_quad(I, q, Y, ld, R, 0, 1);
+    __shared__ double red[RBLOCK / 64];
+    for (int q = 0; q < I.nlc; ++q) {
+      if (I.lc_off[q + 1] - I.lc_off[q] <= 8) continue;
+      double v = wave_sum(lc_quad(I, q, Y, ld, R, threadIdx.x, blockDim.x));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+        out[q] = s;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // coefficients blockdiag(y_l D_q) Y: lc_Z slot zsel (rk x R_MAX) or lc_zv (vector)
+  const double *y = a.mult ? a.mult : I.yp;
+  double *Z = vec ? I.lc_zv : I.lc_Z + (size_t)a.zsel * rk * R_MAX;
+  for (int q2 = threadIdx.x; q2 < rk * R; q2 += blockDim.x) {
+    const int k = q2 / R, c = q2 - (q2 / R) * R;
+    const int q = lc_term_of(I, k);
+    const int o = I.lc_off[q], rl = I.lc_off[q + 1] - o, ai = k - o;
+    const double *Dq = I.Dc + I.lc_doff[q];
+    double s = 0.0;
+    for (int b = 0; b < rl; ++b) s += Dq[(size_t)ai * rl + b] * Y[(size_t)(o + b) * ld + c];
+    Z[(size_t)k * ld + c] = y[I.lc_con[q] - 1] * s;
+  }
+}
+
 // Parameters of a standalone operator call, passed by value as the kernel's
 // argument (captured when the launch is enqueued, so nothing host-side has to
 // stay unchanged until the stream reaches it).
 __global__ void k_put_params(InstParams *dst, InstParams v) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+template <typename T, int G>
+static void l_lc_kty(hipStream_t s, const Tile *t, int nt, const InstDev *d, int ncg, int xrole, int vsrc) {
+  hipLaunchKernelGGL((k_lc_kty<T, G>), dim3(nt, ncg), dim3(BLOCK), 0, s, t, d, xrole, vsrc);
+}
+void op_lc_kty(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int max_rk, int xrole, int vsrc) {
+  if (nt <= 0 || max_rk <= 0) return;
+  const int ncg = (max_rk + 63) / 64;
+  if (vsrc != 0) R = is64(prec) ? 2 : 4;  // the vector forms read FP64 K and v: any instantiation
+  if (is64(prec)) HL_DISPATCH_G(double, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
+  else HL_DISPATCH_G(float, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
+}
+void op_lc_red(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int mode, int R, int zsel,
+               const double *mult) {
+  if (ni <= 0) return;
+  LcArgs a{mode, R, zsel, mult};
+  hipLaunchKernelGGL(k_lc_red, dim3(ni), dim3(RBLOCK), 0, s, ilist, d, a);
 }
 void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v) {
   hipLaunchKernelGGL(k_put_params, dim3(1), dim3(64), 0, s, dst, v);

@@ -14,6 +14,12 @@ enum RedOpH : int {
 };
 
 void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v);
+// Constraints' low-rank parts: partial K^T X per tile (vsrc 0: role xrole of
+// R columns; 1: the Lanczos vector being multiplied; 2: the Ritz vector),
+// then per instance the mode's reduction (LcMode).
+void op_lc_kty(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int max_rk, int xrole, int vsrc);
+void op_lc_red(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int mode, int R, int zsel,
+               const double *mult = nullptr);
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp,
               double *tout = nullptr);
 void op_lr_dots(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole);

@@ -39,6 +39,14 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
       *code = HALLAR_E_NUMERICAL;
       return "b has NaN/Inf";
     }
+  if (p->n_lowrank < 0) return "n_lowrank < 0";
+  if (p->n_lowrank > 0 && (!p->lr_con || !p->lr_rank || !p->K || !p->D)) return "low-rank arrays are NULL";
+  bool has_lc = false;
+  for (int32_t t = 0; t < p->n_lowrank; ++t) {
+    if (p->lr_con[t] < 0 || p->lr_con[t] > m) return "lr_con out of range";
+    if (p->lr_rank[t] < 1) return "lr_rank must be >= 1";
+    if (p->lr_con[t] > 0) has_lc = true;
+  }
   std::vector<Ent> e((size_t)p->nnz);
   for (int64_t k = 0; k < p->nnz; ++k) {
     const int32_t i = p->row[k], j = p->col[k], l = p->con[k];
@@ -106,6 +114,8 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
   }
   for (int l = 0; l < m; ++l)
     if (ccount[l] != 1) direct = false;
+  // a constraint with a low-rank part sums more than its pairs
+  if (has_lc) direct = false;
   for (int i = 0; i < n; ++i) hp.rowptr_u[i + 1] += hp.rowptr_u[i];
   hp.direct = direct;
   hp.has_c = has_c;
@@ -211,33 +221,84 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
       if (hp.pcon[hp.pid_l[e]] <= 0) low = false;
     hp.low_recompute = low;
   }
-  // low-rank part (objective only)
-  if (p->n_lowrank < 0) return "n_lowrank < 0";
-  if (p->n_lowrank > 1) {
-    *code = HALLAR_E_UNSUPPORTED;
-    return "at most one low-rank term is supported";
-  }
-  if (p->n_lowrank == 1) {
-    if (!p->lr_con || !p->lr_rank || !p->K || !p->D) return "low-rank arrays are NULL";
-    if (p->lr_con[0] < 0 || p->lr_con[0] > m) return "lr_con out of range";
-    if (p->lr_con[0] != 0) {
-      *code = HALLAR_E_UNSUPPORTED;
-      return "low-rank terms on constraints are not supported";
+  // low-rank parts (Section 3.2, eq. HSLR-rep-body, Algorithms 3 and 5): the
+  // objective's (at most one term, rank <= LR_MAX) and the constraints' (any
+  // number of terms of any rank; the terms of one constraint are merged)
+  {
+    std::vector<int32_t> obj;
+    std::vector<std::vector<int32_t>> per(m);
+    for (int32_t t = 0; t < p->n_lowrank; ++t) {
+      if (p->lr_con[t] == 0) obj.push_back(t);
+      else per[p->lr_con[t] - 1].push_back(t);
     }
-    const int r0 = p->lr_rank[0];
-    if (r0 < 1 || r0 > LR_MAX) {
-      *code = HALLAR_E_UNSUPPORTED;
-      return "low-rank objective rank must be 1 or 2";
-    }
-    const int64_t ko = p->K_off ? p->K_off[0] : 0, dof = p->D_off ? p->D_off[0] : 0;
-    hp.r0 = r0;
-    hp.K0.assign(p->K + ko, p->K + ko + (int64_t)n * r0);
-    hp.D0.assign(p->D + dof, p->D + dof + r0 * r0);
-    for (double v : hp.K0)
-      if (!std::isfinite(v)) {
+    auto kof = [&](int32_t t) { return p->K_off ? p->K_off[t] : (int64_t)0; };
+    auto dof = [&](int32_t t) { return p->D_off ? p->D_off[t] : (int64_t)0; };
+    auto finite_block = [&](int32_t t) {
+      const int r = p->lr_rank[t];
+      for (int64_t q = 0; q < (int64_t)n * r; ++q)
+        if (!std::isfinite(p->K[kof(t) + q])) return false;
+      for (int64_t q = 0; q < (int64_t)r * r; ++q)
+        if (!std::isfinite(p->D[dof(t) + q])) return false;
+      return true;
+    };
+    for (int32_t t = 0; t < p->n_lowrank; ++t)
+      if (!finite_block(t)) {
         *code = HALLAR_E_NUMERICAL;
-        return "K has NaN/Inf";
+        return "K or D has NaN/Inf";
       }
+    if (obj.size() > 1) {
+      *code = HALLAR_E_UNSUPPORTED;
+      return "at most one low-rank objective term is supported";
+    }
+    if (obj.size() == 1) {
+      const int32_t t = obj[0];
+      const int r0 = p->lr_rank[t];
+      if (r0 > LR_MAX) {
+        *code = HALLAR_E_UNSUPPORTED;
+        return "low-rank objective rank must be 1 or 2";
+      }
+      hp.r0 = r0;
+      hp.K0.assign(p->K + kof(t), p->K + kof(t) + (int64_t)n * r0);
+      hp.D0.assign(p->D + dof(t), p->D + dof(t) + r0 * r0);
+    }
+    int64_t rk = 0;
+    for (int l = 0; l < m; ++l)
+      for (int32_t t : per[l]) rk += p->lr_rank[t];
+    if (rk > RK_MAX) {
+      *code = HALLAR_E_UNSUPPORTED;
+      return "the constraints' low-rank parts have more than " + std::to_string(RK_MAX) + " columns";
+    }
+    hp.rk = (int32_t)rk;
+    hp.lc_of_con.assign(m, -1);
+    if (rk > 0) {
+      hp.Kc.assign((size_t)n * rk, 0.0);
+      hp.lc_off.push_back(0);
+      int32_t col = 0;
+      int64_t doff = 0;
+      for (int l = 0; l < m; ++l) {
+        if (per[l].empty()) continue;
+        int32_t rl = 0;
+        for (int32_t t : per[l]) rl += p->lr_rank[t];
+        hp.lc_of_con[l] = (int32_t)hp.lc_con.size();
+        hp.lc_con.push_back(l + 1);
+        hp.lc_doff.push_back((int32_t)doff);
+        std::vector<double> Dl((size_t)rl * rl, 0.0);
+        int32_t c0 = 0;
+        for (int32_t t : per[l]) {
+          const int r = p->lr_rank[t];
+          for (int32_t i = 0; i < n; ++i)
+            for (int a = 0; a < r; ++a) hp.Kc[(size_t)i * rk + col + c0 + a] = p->K[kof(t) + (int64_t)i * r + a];
+          for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b) Dl[(size_t)(c0 + a) * rl + c0 + b] = p->D[dof(t) + a * r + b];
+          c0 += r;
+        }
+        hp.Dc.insert(hp.Dc.end(), Dl.begin(), Dl.end());
+        doff += (int64_t)rl * rl;
+        col += rl;
+        hp.lc_off.push_back(col);
+      }
+      hp.nlc = (int32_t)hp.lc_con.size();
+    }
   }
   // norms for eq. termination2
   double bl1 = 0.0;

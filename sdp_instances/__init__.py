@@ -336,6 +336,55 @@ def mc_planted(n1: int, n2: int, r: int, m: int, seed: int = 4) -> Problem:
     return p
 
 
+def phaselift_real(n: int, m: int, seed: int = 1) -> Problem:
+    """Real-valued phase retrieval SDP (the real analogue of Section 5.4's
+    complex formulation): min tr(X) s.t. a_l^T X a_l = (a_l^T x)^2, l = 1..m,
+    with a_l i.i.d. N(0, I) and a planted x ~ N(0, I).  C = I (sparse
+    diagonal), every constraint a rank-one low-rank term K = a_l, D = [1];
+    trace bound tau^2 = ||x||^2, the trace of the planted point x x^T.  With
+    m a few times n the SDP's solution is x x^T (exact recovery), so its value
+    is ||x||^2."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n)
+    A = rng.standard_normal((m, n))
+    i = np.arange(n)
+    return Problem(name=f"phaselift_real_n{n}_m{m}_s{seed}", n=n, m=m, tau2=float(x @ x), row=i, col=i,
+                   con=np.zeros(n, np.int64), val=np.ones(n), b=(A @ x) ** 2,
+                   lr_con=list(range(1, m + 1)), lr_K=[A[l].reshape(n, 1) for l in range(m)],
+                   lr_D=[np.ones((1, 1)) for _ in range(m)], meta={"kind": "phaselift", "x": x})
+
+
+def lowrank_constraints(n: int, m: int, seed: int = 1) -> Problem:
+    """Random HSLR instance whose constraints mix the two parts of eq.
+    HSLR-rep-body: the first 2m/3 constraints have sparse entries, the last
+    2m/3 have a low-rank term K_l D_l K_l^T of rank 1 to 3 (the middle third
+    both), one constraint two terms; the objective has a sparse part and a
+    rank-2 low-rank term; b random (operator and eigen tests)."""
+    rng = np.random.default_rng(seed)
+    rows, cols, cons, vals = [], [], [], []
+    for l in range(0, m):
+        if l < 2 * m // 3:
+            for _ in range(3):
+                i, j = sorted(rng.integers(0, n, 2))
+                rows.append(i); cols.append(j); cons.append(l + 1); vals.append(rng.standard_normal())
+    for _ in range(2 * n):
+        i, j = sorted(rng.integers(0, n, 2))
+        rows.append(i); cols.append(j); cons.append(0); vals.append(rng.standard_normal())
+    lr_con, lr_K, lr_D = [0], [rng.standard_normal((n, 2)) / np.sqrt(n)], [np.diag([1.0, -0.5])]
+    for l in range(m // 3, m):
+        r = int(rng.integers(1, 4))
+        lr_con.append(l + 1)
+        lr_K.append(rng.standard_normal((n, r)) / np.sqrt(n))
+        D = rng.standard_normal((r, r))
+        lr_D.append(D + D.T)
+    lr_con.append(m)
+    lr_K.append(rng.standard_normal((n, 1)) / np.sqrt(n))
+    lr_D.append(np.array([[0.3]]))
+    return Problem(name=f"lowrank_constraints_n{n}_m{m}_s{seed}", n=n, m=m, tau2=1.0, row=rows, col=cols, con=cons,
+                   val=vals, b=0.01 * rng.standard_normal(m), lr_con=lr_con, lr_K=lr_K, lr_D=lr_D,
+                   meta={"kind": "random"})
+
+
 def served_stream_sizes(count: int = 4096, seed: int = 5, nmin: int = 100, nmax: int = 20_000):
     """Sizes of the served request stream: n log-uniform in [nmin, nmax]."""
     rng = np.random.default_rng(seed)

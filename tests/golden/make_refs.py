@@ -15,6 +15,7 @@ import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
 import sdp_instances as si  # noqa: E402
+from sdp_instances.sdpa import random_sdpa_text, read_sdpa  # noqa: E402
 
 
 def cases():
@@ -32,6 +33,9 @@ def cases():
     for n in (37, 150, 420, 1100):
         i, j = si.er_edges(n, 8.0 / (n - 1), rng)
         yield f"pool_er{n}", si.maxcut_problem(n, i, j, si.pm1_weights(i.size, rng)), {}, 1e-7
+    # an SDPA problem with one dense constraint (split to a low-rank term)
+    text, tr = random_sdpa_text(24, 8, seed=3)
+    yield "sdpa_dense_24", read_sdpa(text, 3.0 * tr), {}, 1e-6
 
 
 def main(only):

@@ -61,9 +61,25 @@ def test_descriptor_validation():
     q = si.random_hslr(8, 4, 0)
     q.val = q.val.copy(); q.val[3] = np.nan
     _bad(q, 9)
-    # low-rank term on a constraint: unsupported by the library
-    q = si.random_hslr(8, 4, 0, lowrank_nonobjective=True)
+    # two low-rank objective terms, or one of rank 3: unsupported by the library
+    q = si.random_hslr(8, 4, 0)
+    q.lr_con = [0, 0]; q.lr_K = [q.lr_K[0], q.lr_K[0]]; q.lr_D = [q.lr_D[0], q.lr_D[0]]
     _bad(q, 2)
+    q = si.random_hslr(8, 4, 0)
+    q.lr_K = [np.ones((8, 3))]; q.lr_D = [np.eye(3)]
+    _bad(q, 2)
+    # constraints' low-rank parts beyond 4096 columns in all
+    q = si.random_hslr(8, 4, 0)
+    q.lr_con = [1, 2]; q.lr_K = [np.ones((8, 2048)), np.ones((8, 2049))]; q.lr_D = [np.eye(2048), np.eye(2049)]
+    _bad(q, 2)
+    # a low-rank term on a constraint out of range
+    q = si.random_hslr(8, 4, 0, lowrank_nonobjective=True)
+    q.lr_con = [0, 5]
+    _bad(q, 1)
+    # low-rank terms on constraints are supported: footprint and structure without a device
+    q = si.random_hslr(8, 4, 0, lowrank_nonobjective=True)
+    assert H.hallar_footprint(q) > H.hallar_footprint(si.random_hslr(8, 4, 0))
+    assert H.hallar_inspect(q)["direct"] == 0
     # a valid one has a positive, deterministic footprint
     b1 = H.hallar_footprint(p)
     b2 = H.hallar_footprint(p)

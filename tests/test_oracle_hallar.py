@@ -281,3 +281,15 @@ def test_theta_hamming_closed_form(d):
     assert res.status == "ok"
     assert abs(res.pval + n / 2) <= 1e-5 * (1 + n / 2)
     assert max(res.pinf, res.gap, res.dinf) <= 1e-5
+
+
+def test_phaselift_real_exact_recovery():
+    """Real phase retrieval SDP with a rank-one low-rank term per constraint
+    (the real analogue of Section 5.4): with m = 6n Gaussian measurements the
+    solution is the planted x x^T, so the value is ||x||^2 (exact recovery)."""
+    prob = si.phaselift_real(20, 120, seed=1)
+    x = prob.meta["x"]
+    res = oracle.hallar(prob, si.gaussian_u0(prob.n, 7), oracle.Options(eps=1e-6))
+    assert res.status == "ok"
+    assert abs(res.pval - x @ x) <= 1e-5 * (1 + x @ x)
+    assert np.linalg.norm(res.U @ res.U.T - np.outer(x, x)) <= 1e-2 * (x @ x)
