@@ -11,6 +11,12 @@ Definitions followed (cuHALLaR paper, arXiv 2505.13719):
   * Section 2, eq. (AL function): L_beta(X; p) = C.X + p^T(A(X)-b) + beta/2 ||A(X)-b||^2.
   * Section 2, eq. (Grad U Space):
         grad_U L_beta(UU^T; p) = 2 [C + A*(p + beta (A(UU^T) - b))] U.
+  * Section 5.4, eq. (phase retrieval SDP): constraints <a a^H, X> on a
+    complex Hermitian X, here with coded-diffraction vectors: a_{l,k}^H u is
+    the k-th entry of the unitary DFT of d_l * u.  The SDP is taken on its
+    real form: a real column z of U is u = z[:n/2] + i z[n/2:], so that
+    <a a^H, sum_c u_c u_c^H> = sum_c |a^H u_c|^2 (and Tr X = ||U||_F^2);
+    the adjoint sum_k y_k a_k (a_k^H u) is D_l^H F^H (y_l * F D_l u).
 """
 from __future__ import annotations
 
@@ -20,6 +26,13 @@ import scipy.sparse as sp
 
 def _rowdot(U, i, j):
     return np.einsum("kr,kr->k", U[i], U[j])
+
+
+def _cdp_spectra(prob, U):
+    """F (d_l * u_c) for every pattern l and column c: shape (L, n_c, r)."""
+    nc = prob.n // 2
+    Uc = U[:nc] + 1j * U[nc:]
+    return np.fft.fft(prob.cdp_masks[:, :, None] * Uc[None, :, :], axis=1, norm="ortho")
 
 
 def a_tilde(prob, U):
@@ -37,6 +50,9 @@ def a_tilde(prob, U):
     for l, K, D in zip(prob.lr_con, prob.lr_K, prob.lr_D):
         Y = K.T @ U
         T[l] += float(np.sum(D * (Y @ Y.T)))
+    if getattr(prob, "cdp_masks", None) is not None:
+        # |a_{l,k}^H u_c|^2 summed over the columns, constraint l n_c + k
+        T[1:] += (np.abs(_cdp_spectra(prob, U)) ** 2).sum(axis=2).reshape(-1)
     return T
 
 
@@ -66,6 +82,12 @@ def adjoint_apply(prob, ptilde, U):
     ptilde = np.asarray(ptilde, np.float64)
     for l, K, D in zip(prob.lr_con, prob.lr_K, prob.lr_D):
         W += ptilde[l] * (K @ (D @ (K.T @ U2)))
+    if getattr(prob, "cdp_masks", None) is not None:
+        L, nc = prob.cdp_masks.shape
+        y = ptilde[1:].reshape(L, nc, 1)
+        back = np.fft.ifft(y * _cdp_spectra(prob, U2), axis=1, norm="ortho")
+        V = (np.conj(prob.cdp_masks)[:, :, None] * back).sum(axis=0)
+        W += np.vstack([V.real, V.imag])
     return W.reshape(-1) if vec else W
 
 

@@ -63,6 +63,13 @@ class Problem:
     lr_K: List[np.ndarray] = field(default_factory=list)
     lr_D: List[np.ndarray] = field(default_factory=list)
     meta: dict = field(default_factory=dict)
+    # coded-diffraction constraints of complex phase retrieval (Section 5.4),
+    # stated on the real form of the complex Hermitian variable: n = 2 n_c,
+    # a real column z of U is the complex vector u = z[:n_c] + i z[n_c:], and
+    # constraint l n_c + k (0-based) is sum_c |(F (d_l * u_c))_k|^2 with F
+    # the unitary n_c-point DFT and d_l = cdp_masks[l]; there are m = L n_c
+    # of them and no sparse or low-rank constraint entries
+    cdp_masks: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.row = np.ascontiguousarray(self.row, dtype=np.int64)
@@ -78,6 +85,11 @@ class Problem:
             assert (self.row <= self.col).all(), "entries must be upper-triangular (i <= j)"
             assert self.row.min() >= 0 and self.col.max() < self.n
             assert self.con.min() >= 0 and self.con.max() <= self.m
+        if self.cdp_masks is not None:
+            self.cdp_masks = np.ascontiguousarray(self.cdp_masks, dtype=np.complex128)
+            L, nc = self.cdp_masks.shape
+            assert self.n == 2 * nc and self.m == L * nc
+            assert not self.lr_con and (self.con == 0).all(), "coded-diffraction problems take C only as entries"
 
     @property
     def nnz(self) -> int:
@@ -352,6 +364,36 @@ def phaselift_real(n: int, m: int, seed: int = 1) -> Problem:
                    con=np.zeros(n, np.int64), val=np.ones(n), b=(A @ x) ** 2,
                    lr_con=list(range(1, m + 1)), lr_K=[A[l].reshape(n, 1) for l in range(m)],
                    lr_D=[np.ones((1, 1)) for _ in range(m)], meta={"kind": "phaselift", "x": x})
+
+
+def cdp_masks(nc: int, L: int, rng: np.random.Generator) -> np.ndarray:
+    """L octanary coded-diffraction masks of length nc: each entry is
+    b1 * b2 with b1 uniform on {1, -1, i, -i} and b2 = sqrt(2)/2 with
+    probability 0.8, sqrt(3) with probability 0.2 (the modulation of Candes,
+    Li and Soltanolkotabi, "Phase retrieval from coded diffraction
+    patterns", 2015; E|d|^2 = 1)."""
+    b1 = np.array([1.0, -1.0, 1j, -1j])[rng.integers(0, 4, size=(L, nc))]
+    b2 = np.where(rng.random((L, nc)) < 0.8, math.sqrt(2.0) / 2.0, math.sqrt(3.0))
+    return b1 * b2
+
+
+def phase_retrieval_cdp(nc: int, L: int = 12, seed: int = 1) -> Problem:
+    """Complex phase retrieval from L coded diffraction patterns (Section
+    5.4, eq. phase retrieval SDP; m = 12 n as in the paper's table):
+    x in C^nc with i.i.d. standard complex Gaussian entries, measurements
+    b_{l,k} = |(F (d_l * x))_k|^2 with F the unitary DFT.  The SDP
+    min Tr X s.t. <a a^H, X> = b, X Hermitian PSD is stated on its real form
+    (n = 2 nc, C = I as diagonal entries, see Problem.cdp_masks); the trace
+    bound is ||x||^2.  With this many patterns the SDP recovers x x^H, so
+    its optimum is ||x||^2."""
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal(nc) + 1j * rng.standard_normal(nc)) / math.sqrt(2.0)
+    d = cdp_masks(nc, L, rng)
+    b = np.abs(np.fft.fft(d * x[None, :], axis=1, norm="ortho")) ** 2
+    i = np.arange(2 * nc)
+    return Problem(name=f"phase_cdp_n{nc}_L{L}_s{seed}", n=2 * nc, m=L * nc, tau2=float(np.vdot(x, x).real),
+                   row=i, col=i, con=np.zeros(2 * nc, np.int64), val=np.ones(2 * nc), b=b.reshape(-1),
+                   cdp_masks=d, meta={"kind": "phase_cdp", "x": x, "L": L})
 
 
 def lowrank_constraints(n: int, m: int, seed: int = 1) -> Problem:
