@@ -86,6 +86,21 @@ typedef struct {
   const int64_t *K_off, *D_off;
   const double *K, *D;
   const double *b;       /* length m */
+  /* Coded-diffraction constraints of complex phase retrieval (Section 5.4,
+   * eq. phase retrieval SDP), applied on the fly with FFTs instead of being
+   * stored.  cdp_patterns = L > 0 states the SDP on the real form of the
+   * complex Hermitian variable: n = 2 n_c, a real column z of U stands for
+   * u = z[0:n_c] + i z[n_c:n] (so Tr X = ||U||_F^2), and constraint
+   * l n_c + k (0-based, l < L, k < n_c) is
+   *   A_{l n_c + k} . UU^T = sum_c |(F (d_l * u_c))_k|^2,
+   * F the unitary n_c-point DFT and d_l the l-th mask, complex, interleaved
+   * (re, im) in cdp_masks[2 (l n_c + j) + {0, 1}] (host, L n_c pairs, read
+   * during hallar_create only).  Then m = L n_c, and the problem may hold
+   * only objective entries (con = 0) and no low-rank terms; otherwise
+   * HALLAR_E_INVALID (shapes) or HALLAR_E_UNSUPPORTED (mixtures).
+   * cdp_patterns = 0: no such constraints (cdp_masks ignored). */
+  int32_t cdp_patterns;
+  const double *cdp_masks;
 } hallar_problem;
 
 /* Solver constants.  hallar_default_options() fills the values the library
@@ -318,11 +333,13 @@ hallar_status hallar_pool_usage(hallar_pool_t pool, size_t *used, size_t *budget
  * around each launch: 0 SDDMM (A~(UU^T) + AL epilogue), 1 SpMM
  * ((C + A*(y))U + epilogue), 2 Lanczos SpMV, 3 Lanczos reorthogonalisation,
  * 4 vector updates, 5 reductions, 6 other, 7 the fused FISTA trial kernel
- * (SDDMM and gradient SpMM in one row walk).  For each class: total
+ * (SDDMM and gradient SpMM in one row walk), 8 the coded-diffraction
+ * operator (mask products, FFTs, |.|^2 sums, multiplier scaling and the
+ * gather of the adjoint block; Section 5.4).  For each class: total
  * milliseconds, launches, and algorithmic bytes (every index, value and
  * constraint array read once, U read once, outputs written once).  Counters
  * accumulate since the handle/pool was created or last reset (reset != 0).
- * Arrays are host, length n_classes (<= 8). */
+ * Arrays are host, length n_classes (<= 9). */
 hallar_status hallar_profile(hallar_t h, double *ms, int64_t *launches, double *bytes, int32_t n_classes, int32_t reset);
 hallar_status hallar_pool_profile(hallar_pool_t pool, double *ms, int64_t *launches, double *bytes, int32_t n_classes,
                                   int32_t reset);

@@ -419,6 +419,8 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
   for (int k = 0; k < count; ++k) {
     hl::Slot &src = *hs[k]->P.slots[0];
     auto v = std::make_unique<hl::Slot>();
+    // every scalar of the preprocessed problem the round executor reads
+    // (the index arrays stay with the handle: the device copies are used)
     v->hp.n = src.hp.n;
     v->hp.m = src.hp.m;
     v->hp.tau2 = src.hp.tau2;
@@ -429,10 +431,20 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     v->hp.low_recompute = src.hp.low_recompute;
     v->hp.con_rule = src.hp.con_rule;
     v->hp.has_c = src.hp.has_c;
+    v->hp.pa_uniform = src.hp.pa_uniform;
+    v->hp.pa_const = src.hp.pa_const;
+    v->hp.c_diag_only = src.hp.c_diag_only;
     v->hp.r0 = src.hp.r0;
+    v->hp.rk = src.hp.rk;
+    v->hp.nlc = src.hp.nlc;
+    v->hp.cdp_L = src.hp.cdp_L;
+    v->hp.cdp_nc = src.hp.cdp_nc;
     v->hp.b_l1 = src.hp.b_l1;
     v->hp.c_l1 = src.hp.c_l1;
+    v->hp.tile_min_rows = src.hp.tile_min_rows;
+    v->hp.tile_ent_cap = src.hp.tile_ent_cap;
     v->hp.tiles = src.hp.tiles;
+    v->fft = src.fft;  // the handle's FFT plans, used through this view
     for (auto &t : v->hp.tiles) t.inst = k;
     v->Rcap = src.Rcap;
     v->kmax = src.kmax;
@@ -451,7 +463,10 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     B.slots[k] = std::move(v);
     st = prepare_solve(B, k, U0s ? U0s[k] : nullptr, 1, nullptr, msg);
     if (st != HALLAR_OK) {
-      for (int q = 0; q <= k; ++q) B.slots[q]->slab = nullptr;
+      for (int q = 0; q <= k; ++q) {
+        B.slots[q]->slab = nullptr;
+        B.slots[q]->fft = nullptr;
+      }
       hl::pool_release(B);
       return fail(nullptr, st, msg);
     }
@@ -470,6 +485,7 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     src.cur_R = v.cur_R;
     src.result = v.result;
     v.slab = nullptr;  // views: do not free
+    v.fft = nullptr;
   }
   const std::string berr = B.err;
   hl::pool_release(B);

@@ -12,8 +12,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <random>
+
+#include <rocfft/rocfft.h>
 
 #include "ops.h"
 
@@ -163,6 +168,7 @@ struct Layout {
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, m64_low, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
       ilist;
   size_t Kc, Kc64, Dc, lc_con, lc_off, lc_doff, lc_of_con, lc_part, lc_Y, lc_Z, lc_T, lc_v, lc_zv, lc_Tv;
+  size_t cdp_d, cdp_S, cdp_S2, cdp_T, cdp_Tv, cdp_wv, cdp_W[2];
   size_t total;
 };
 
@@ -240,6 +246,18 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
     L.lc_v = c.take(rk * 8);
     L.lc_zv = c.take(rk * 8);
     L.lc_Tv = c.take(nlc * 8);
+  }
+  if (hp.cdp_L > 0) {
+    // masks, spectra for up to Rcap columns (and their scaled copy), the
+    // constraint values, the adjoint blocks of the two Z-slots
+    const size_t nc = hp.cdp_nc, Lp = hp.cdp_L;
+    L.cdp_d = c.take(Lp * nc * 16);
+    L.cdp_S = c.take(Lp * Rcap * nc * 16);
+    L.cdp_S2 = c.take(Lp * Rcap * nc * 16);
+    L.cdp_T = c.take(m * 8);
+    L.cdp_Tv = c.take(m * 8);
+    L.cdp_wv = c.take(n * 8);
+    for (int z = 0; z < 2; ++z) L.cdp_W[z] = c.take(n * Rcap * 8);
   }
   L.total = c.off;
   return L;
@@ -354,6 +372,132 @@ static void put(char *base, size_t off, const std::vector<T> &v, hipStream_t st)
   if (!v.empty()) (void)hipMemcpyAsync(base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
+// ------------------------------------------------------------------ FFTs
+// rocFFT plans of a coded-diffraction instance: complex double, length n_c,
+// in place, forward and inverse (both unnormalised), one pair per batch of
+// L r transforms (r the live columns of an operand, 1 for the Lanczos and
+// Frank-Wolfe vectors), made when first needed; one work buffer serves them
+// all (an instance's transforms run one after another on its stream).
+struct CdpFft {
+  struct Pair {
+    rocfft_plan fwd = nullptr, inv = nullptr;
+  };
+  size_t len = 0;
+  std::map<int, Pair> plans;
+  rocfft_execution_info info = nullptr;
+  void *work = nullptr;
+  size_t work_bytes = 0;
+};
+
+static void cdp_release(CdpFft *F) {
+  if (!F) return;
+  for (auto &kv : F->plans) {
+    if (kv.second.fwd) rocfft_plan_destroy(kv.second.fwd);
+    if (kv.second.inv) rocfft_plan_destroy(kv.second.inv);
+  }
+  if (F->info) rocfft_execution_info_destroy(F->info);
+  if (F->work) (void)hipFree(F->work);
+  delete F;
+}
+
+// The plan pair for `batch` transforms, made on first use.  A work buffer
+// larger than the one held is allocated after the device has drained (the
+// old one may still be in use by transforms already enqueued).
+static const CdpFft::Pair *cdp_plan(CdpFft &F, int batch, std::string &err) {
+  auto it = F.plans.find(batch);
+  if (it != F.plans.end()) return &it->second;
+  CdpFft::Pair pr;
+  if (rocfft_plan_create(&pr.fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward,
+                         rocfft_precision_double, 1, &F.len, (size_t)batch, nullptr) != rocfft_status_success ||
+      rocfft_plan_create(&pr.inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse,
+                         rocfft_precision_double, 1, &F.len, (size_t)batch, nullptr) != rocfft_status_success) {
+    if (pr.fwd) rocfft_plan_destroy(pr.fwd);
+    err = "rocfft_plan_create failed (length " + std::to_string(F.len) + ", batch " + std::to_string(batch) + ")";
+    return nullptr;
+  }
+  size_t need = 0;
+  for (rocfft_plan pl : {pr.fwd, pr.inv}) {
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(pl, &wb) == rocfft_status_success) need = std::max(need, wb);
+  }
+  if (need > F.work_bytes) {
+    (void)hipDeviceSynchronize();
+    if (F.work) (void)hipFree(F.work);
+    F.work = nullptr;
+    F.work_bytes = 0;
+    if (hipMalloc(&F.work, need) != hipSuccess ||
+        rocfft_execution_info_set_work_buffer(F.info, F.work, need) != rocfft_status_success) {
+      rocfft_plan_destroy(pr.fwd);
+      rocfft_plan_destroy(pr.inv);
+      err = "FFT work buffer allocation failed";
+      return nullptr;
+    }
+    F.work_bytes = need;
+  }
+  return &(F.plans[batch] = pr);
+}
+
+static hallar_status cdp_plans(const HostProblem &h, int prec, int Rcap, CdpFft *&out, std::string &err) {
+  static std::once_flag once;
+  static rocfft_status setup = rocfft_status_success;
+  std::call_once(once, [] { setup = rocfft_setup(); });
+  if (setup != rocfft_status_success) {
+    err = "rocfft_setup failed";
+    return HALLAR_E_HIP;
+  }
+  CdpFft *F = new CdpFft;
+  F->len = (size_t)h.cdp_nc;
+  if (rocfft_execution_info_create(&F->info) != rocfft_status_success) {
+    cdp_release(F);
+    err = "rocfft_execution_info_create failed";
+    return HALLAR_E_HIP;
+  }
+  // the widest batch first (its work buffer is the largest), then the vectors'
+  (void)prec;
+  if (!cdp_plan(*F, h.cdp_L * Rcap, err) || !cdp_plan(*F, h.cdp_L, err)) {
+    cdp_release(F);
+    return HALLAR_E_HIP;
+  }
+  out = F;
+  return HALLAR_OK;
+}
+
+// one batch of in-place transforms on the instance's stream
+static void cdp_exec(Pool &P, CdpFft &F, int batch, bool forward, void *buf, hipStream_t st) {
+  const CdpFft::Pair *pr = cdp_plan(F, batch, P.err);
+  if (!pr) {
+    std::fprintf(stderr, "[hallar] %s\n", P.err.c_str());
+    return;
+  }
+  (void)rocfft_execution_info_set_stream(F.info, st);
+  void *io[1] = {buf};
+  (void)rocfft_execute(forward ? pr->fwd : pr->inv, io, nullptr, F.info);
+}
+
+// Spectra F (d_l * u_c) of the first Rc columns of role xrole (vsrc 0, rows
+// of stride R) or of a vector (vsrc 1: the Lanczos vector, 2: the Ritz
+// vector; R = Rc = 1), and when out >= 0 their |.|^2 sums into cdp_T (out 0)
+// or cdp_Tv (out 1).
+static void cdp_forward(Pool &P, int s, hipStream_t st, int xrole, int vsrc, int R, int Rc, int out) {
+  Slot &S = *P.slots[s];
+  const size_t L = S.hp.cdp_L, nc = S.hp.cdp_nc;
+  op_cdp_pack(P.prec, st, P.d_insts, s, xrole, vsrc, R, Rc, L * Rc * nc);
+  cdp_exec(P, *S.fft, (int)(L * Rc), true, S.dev.cdp_S, st);
+  if (out >= 0) op_cdp_abs2(st, P.d_insts, s, Rc, out, L * nc);
+}
+
+// The adjoint block sum_l conj(d_l) F^H (y_l * spectra) of the last
+// cdp_forward (Rc columns), with multipliers mult (null: the instance's y'),
+// into cdp_W[zsel] (vec 0, R columns, those from Rc on zero) or cdp_wv
+// (vec 1, R = Rc = 1).
+static void cdp_adjoint(Pool &P, int s, hipStream_t st, int R, int Rc, int zsel, int vec, const double *mult) {
+  Slot &S = *P.slots[s];
+  const size_t L = S.hp.cdp_L, nc = S.hp.cdp_nc;
+  op_cdp_scale(st, P.d_insts, s, Rc, mult, L * Rc * nc);
+  cdp_exec(P, *S.fft, (int)(L * Rc), false, S.dev.cdp_S2, st);
+  op_cdp_gather(st, P.d_insts, s, R, Rc, zsel, vec, (size_t)R * nc);
+}
+
 hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   P.tile_epoch++;
   auto sl = std::make_unique<Slot>();
@@ -364,10 +508,16 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   S.Rcap = rcap_for(P.opts, P.prec);
   S.kmax = kmax_for(P.opts, h.n);
   const Layout L = make_layout(h, P.prec, S.Rcap, S.kmax);
+  if (h.cdp_L > 0) {
+    const hallar_status fs = cdp_plans(h, P.prec, S.Rcap, S.fft, err);
+    if (fs != HALLAR_OK) return fs;
+  }
   char *base = nullptr;
   if (P.use_arena) {
     const size_t off = P.arena.alloc(L.total);
     if (off == SIZE_MAX) {
+      cdp_release(S.fft);
+      S.fft = nullptr;
       err = "pool budget exhausted";
       return HALLAR_E_OOM;
     }
@@ -375,6 +525,8 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     base = P.arena.base() + off;
   } else {
     if (hipMalloc((void **)&base, L.total) != hipSuccess) {
+      cdp_release(S.fft);
+      S.fft = nullptr;
       err = "hipMalloc of the instance slab failed";
       return HALLAR_E_OOM;
     }
@@ -428,6 +580,11 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     put(base, L.lc_of_con, h.lc_of_con, st);
     (void)hipMemsetAsync(base + L.lc_Z, 0, 2 * (size_t)h.rk * R_MAX * 8, st);
     (void)hipMemsetAsync(base + L.lc_zv, 0, (size_t)h.rk * 8, st);
+  }
+  if (h.cdp_L > 0) {
+    put(base, L.cdp_d, h.cdp_d, st);
+    for (int z = 0; z < 2; ++z) (void)hipMemsetAsync(base + L.cdp_W[z], 0, (size_t)h.n * S.Rcap * 8, st);
+    (void)hipMemsetAsync(base + L.cdp_wv, 0, (size_t)h.n * 8, st);
   }
   put(base, L.tiles, h.tiles, st);
   std::vector<int32_t> il{s};
@@ -527,6 +684,17 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     D.lc_zv = (double *)at(L.lc_zv);
     D.lc_Tv = (double *)at(L.lc_Tv);
   }
+  D.cdp_L = h.cdp_L;
+  D.cdp_nc = h.cdp_nc;
+  if (h.cdp_L > 0) {
+    D.cdp_d = (const double2 *)at(L.cdp_d);
+    D.cdp_S = (double2 *)at(L.cdp_S);
+    D.cdp_S2 = (double2 *)at(L.cdp_S2);
+    D.cdp_T = (double *)at(L.cdp_T);
+    D.cdp_Tv = (double *)at(L.cdp_Tv);
+    D.cdp_wv = (double *)at(L.cdp_wv);
+    for (int z = 0; z < 2; ++z) D.cdp_W[z] = (double *)at(L.cdp_W[z]);
+  }
   S.dev = D;
   S.used = true;
   S.free_bufs.clear();
@@ -535,6 +703,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
   S.prm.tau2 = h.tau2;
   S.prm.tau = std::sqrt(h.tau2);
   S.cur_R = r_bucket(1, P.prec);
+  S.cur_r = 1;
   P.slots[s] = std::move(sl);
   P.insts_dirty = true;
   // tiles / ilist of the slot live in its slab
@@ -553,6 +722,8 @@ void slot_unload(Pool &P, int s) {
     if (P.use_arena) P.arena.free(S.slab_off, S.slab_bytes);
     else (void)hipFree(S.slab);
   }
+  cdp_release(S.fft);
+  S.fft = nullptr;
   P.slots[s].reset();
   P.h_insts[s] = InstDev{};
   P.insts_dirty = true;
@@ -604,7 +775,8 @@ struct ProfScope {
   double bytes;
   hipStream_t st;
   ProfScope(Pool &p, int c, double b, hipStream_t s) : P(p), cls(c), bytes(b), st(s) {
-    const bool timed = P.prof_level == 1 || c == KC_SDDMM || c == KC_SPMM || c == KC_FUSED || c == KC_LZ_SPMV;
+    const bool timed =
+        P.prof_level == 1 || c == KC_SDDMM || c == KC_SPMM || c == KC_FUSED || c == KC_LZ_SPMV || c == KC_CDP;
     if (P.profile && timed && P.ev_used + 2 <= (int)P.events.size()) {
       e0 = P.ev_used;
       P.ev_used += 2;
@@ -638,6 +810,25 @@ struct GroupBytes {
 };
 
 static void launch_group(Pool &P, const Group &g, hipStream_t st);
+
+// Algorithmic bytes of the coded-diffraction operator's steps for Rc live
+// columns of element size xsz in a bucket of R (spectra S = L Rc nc complex
+// doubles, each transform one read and one write of S): part 0 packs
+// d_l * u_c (reads the columns and the masks, writes S) and transforms;
+// part 1 sums |S|^2 into the m constraint values; part 2 scales by the
+// multipliers into S2, transforms back and gathers the n x R block.
+static double cdp_bytes(const HostProblem &h, double xsz, int R, int Rc, int part) {
+  const double S = (double)h.cdp_L * Rc * h.cdp_nc * 16.0, masks = (double)h.cdp_L * h.cdp_nc * 16.0;
+  if (part == 0) return h.n * Rc * xsz + masks + 3.0 * S;
+  if (part == 1) return S + h.m * 8.0;
+  return 2.0 * S + h.m * 8.0 + 2.0 * S + S + masks + h.n * R * 8.0;
+}
+
+// live columns of slot s's pending operation in a group of bucket R
+static int live_cols(const Pool &P, int s, int R) {
+  const int r = P.slots[s]->op.rlive;
+  return r > 0 ? std::min(r, R) : R;
+}
 
 static GroupBytes group_bytes(const Pool &P, const std::vector<int> &slots, int R) {
   GroupBytes b;
@@ -686,6 +877,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
   int64_t max_pb = 0;  // entries of the {p_l, b_l} copies refreshed when p changes
   int64_t max_nl = 0, nrows = 0;
   int max_rk = 0;  // columns of the constraints' low-rank parts
+  std::vector<int> cdps;  // instances with coded-diffraction constraints
   // the trial's SDDMM and gradient SpMM run as one kernel when every instance
   // recomputes its lower half, has no low-rank objective term (its product
   // is reduced between the two) and the rows are narrow
@@ -701,6 +893,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     max_nl = std::max<int64_t>(max_nl, h.nlower);
     nrows += h.n;
     max_rk = std::max(max_rk, h.rk);
+    if (h.cdp_L > 0) cdps.push_back(s);
   }
   // the trial's reduces are split over several workgroups for instances with
   // thousands of tiles (one workgroup then waits on its own loads); each
@@ -714,8 +907,9 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
     op_reduce(st, IL, ni, D, op, zsel, R, (op == RDH_TRIAL_FUSED || op == RDH_YP_PROJ) ? split : 0);
   };
   auto sddmm = [&](int xrole, int msel, int wT, int wyp, int red_op, int zsel) {
-    {
-      ProfScope ps(P, KC_SDDMM, B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0), st);
+    const double sbytes = B.sddmm + (msel >= 0 ? psum * sz : 0.0) + (wT ? 8 * msum : 0.0) + (wyp ? 8 * msum : 0.0);
+    if (cdps.empty()) {
+      ProfScope ps(P, KC_SDDMM, sbytes, st);
       if (any_lr) op_lr_dots(prec, R, st, T, nt, D, xrole);
       op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
       if (gni > 0) {
@@ -729,6 +923,37 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         if (max_rk > 0) op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
         if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
       }
+    } else {
+      // coded-diffraction instances (general mode): their constraint values
+      // before the AL epilogue, their adjoint block after it when the pair
+      // values are formed for an SpMM; timed as a class of their own
+      {
+        ProfScope ps(P, KC_SDDMM, sbytes, st);
+        if (any_lr) op_lr_dots(prec, R, st, T, nt, D, xrole);
+        op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
+        if (max_rk > 0) {
+          op_lc_kty(prec, R, st, T, nt, D, max_rk, xrole, 0);
+          op_lc_red(st, GL, gni, D, LC_Y_T, R, zsel);
+        }
+      }
+      for (int q : cdps) {
+        const HostProblem &h = P.slots[q]->hp;
+        const int rq = live_cols(P, q, R);
+        ProfScope pc(P, KC_CDP, cdp_bytes(h, sz, R, rq, 0) + cdp_bytes(h, sz, R, rq, 1), st);
+        cdp_forward(P, q, st, xrole, 0, R, rq, 0);
+      }
+      {
+        ProfScope po(P, KC_OTHER, 0.0, st);
+        op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
+        if (max_rk > 0) op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
+        if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
+      }
+      if (msel >= 0)
+        for (int q : cdps) {
+          const int rq = live_cols(P, q, R);
+          ProfScope pc(P, KC_CDP, cdp_bytes(P.slots[q]->hp, sz, R, rq, 2), st);
+          cdp_adjoint(P, q, st, R, rq, zsel, 0, nullptr);
+        }
     }
     red(red_op, zsel);
   };
@@ -829,6 +1054,13 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
           op_lc_kty(prec, R, st, T, nt, D, max_rk, 0, 1);
           op_lc_red(st, IL, ni, D, LC_V_LZ, 1, 0);
         }
+        for (int q : cdps) {
+          // the coded-diffraction part of G v_j
+          const HostProblem &h = P.slots[q]->hp;
+          ProfScope pc(P, KC_CDP, cdp_bytes(h, 8.0, 1, 1, 0) + cdp_bytes(h, 8.0, 1, 1, 2), st);
+          cdp_forward(P, q, st, 0, 1, 1, 1, -1);
+          cdp_adjoint(P, q, st, 1, 1, 0, 1, nullptr);
+        }
         {
           // SpMV fused with the first Gram-Schmidt dots
           ProfScope ps(P, KC_LZ_SPMV, B.lz_spmv + vsweep, st);
@@ -856,6 +1088,12 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       }
       break;
     case OP_FW_PREP:
+      for (int q : cdps) {
+        // A(v v^T) of the Ritz vector for the step size
+        const HostProblem &h = P.slots[q]->hp;
+        ProfScope pc(P, KC_CDP, cdp_bytes(h, 8.0, 1, 1, 0) + cdp_bytes(h, 8.0, 1, 1, 1), st);
+        cdp_forward(P, q, st, 0, 2, 1, 1, 1);
+      }
       {
         ProfScope ps(P, KC_OTHER, 0.0, st);
         op_fw_den(st, T, nt, D);
@@ -1034,8 +1272,13 @@ static hallar_status run_round(Pool &P, bool &did_work) {
   // graph stream, no events inside the graph): a batched solve whose
   // multi-group rounds were captured with their side-stream fork and join
   // ended in a host segmentation fault, cause not found, so that form is off.
+  // Rounds of coded-diffraction instances are not captured: their FFTs are
+  // enqueued by rocFFT, whose launches this library does not control.
   bool launched = false, direct_on_gst = false;
-  if (P.opts.graphs && !P.profile && P.gst && groups.size() == 1) {
+  bool any_cdp = false;
+  for (const Group &g : groups)
+    for (int q : g.slots) any_cdp = any_cdp || P.slots[q]->hp.cdp_L > 0;
+  if (P.opts.graphs && !P.profile && P.gst && groups.size() == 1 && !any_cdp) {
     std::vector<int64_t> sig;
     sig.reserve(32 * groups.size() + 8);
     sig.push_back(P.tile_epoch);
@@ -1183,6 +1426,7 @@ struct Ctx {
     const bool vec64 = c == OP_LZ_BEGIN || c == OP_LZ_STEPS || c == OP_LZ_RITZ || c == OP_LZ_RESTART ||
                        c == OP_FW_PREP || c == OP_SETP;
     S.op.R = vec64 ? 0 : S.cur_R;
+    S.op.rlive = vec64 ? 0 : std::min(S.cur_r, S.cur_R);
     return S.op;
   }
 };
@@ -1537,6 +1781,7 @@ static Task compress(Ctx c, int &buf, int &r, int keep_max, bool &truncated) {
   buf = dst;
   r = rnew;
   S.cur_R = RD;
+  S.cur_r = rnew;
 }
 
 static int map_status(int st) {
@@ -1558,6 +1803,7 @@ static Task solve_main(Ctx c) {
   int U = c.alloc();
   int r = std::max(1, S.U0r);
   S.cur_R = r_bucket(r, c.P.prec);
+  S.cur_r = r;
   {
     PendingOp &op = c.op(OP_PACK);
     op.ext = S.U0ext;
@@ -1688,6 +1934,7 @@ static Task solve_main(Ctx c) {
       U = Ynew;
       r = rnew;
       S.cur_R = RD;
+      S.cur_r = rnew;
       // at most R_MAX - 1 columns survive a step, so the next one fits R_MAX
       const int cap = o.rank_cap > 0 ? std::min(o.rank_cap, R_MAX - 1) : R_MAX - 1;
       if (r > cap) {
@@ -1704,6 +1951,7 @@ static Task solve_main(Ctx c) {
           Y = -1;
           r = r_prev;
           S.cur_R = R_prev;
+          S.cur_r = r_prev;
           res.status = HALLAR_E_RANK_CAP;
           break;
         }
@@ -1903,6 +2151,7 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
     op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
     op_lc_red(st, IL, 1, D, LC_Y_T, R, 0);
   }
+  if (S.hp.cdp_L > 0) cdp_forward(P, s, st, RU, 0, R, r, 0);
   if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);
   op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
   HL_TRY(hipMemcpyAsync(T, &P.d_res[s].v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
@@ -1930,8 +2179,8 @@ hallar_status op_eval_AUUt_noalloc(Pool &P, int s, const void *U, int r, int64_t
     return HALLAR_E_HIP;
   }
   const HostProblem &h = S.hp;
-  if (h.rk > 0) {
-    err = "the allocation-free evaluation does not take low-rank constraint terms";
+  if (h.rk > 0 || h.cdp_L > 0) {
+    err = "the allocation-free evaluation does not take low-rank or coded-diffraction constraints";
     return HALLAR_E_UNSUPPORTED;
   }
   const bool u_direct = in_place(U, r, ldu, R);
@@ -2032,6 +2281,11 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
     // blockdiag(p_l D_l) K^T U for the constraints' low-rank parts (Algorithm 5)
     op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
     op_lc_red(st, IL, 1, D, LC_Y_Z, R, 0, p);
+  }
+  if (S.hp.cdp_L > 0) {
+    // the coded-diffraction block D_l^H F^H (p_l * F D_l U)
+    cdp_forward(P, s, st, RU, 0, R, r, -1);
+    cdp_adjoint(P, s, st, R, r, 0, 0, p);
   }
   op_spmm(P.prec, R, st, T_, nt, D, RU, 0, 0, RU2, SPM_PLAIN);
   if (!w_direct) op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);

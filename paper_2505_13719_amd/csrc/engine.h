@@ -58,7 +58,7 @@ class ResumeWorkers {
 };
 
 // kernel classes of the profile
-enum KClass : int { KC_SDDMM = 0, KC_SPMM, KC_LZ_SPMV, KC_LZ_ORTH, KC_VEC, KC_REDUCE, KC_OTHER, KC_FUSED, KC_N };
+enum KClass : int { KC_SDDMM = 0, KC_SPMM, KC_LZ_SPMV, KC_LZ_ORTH, KC_VEC, KC_REDUCE, KC_OTHER, KC_FUSED, KC_CDP, KC_N };
 
 struct ProfRec {
   int cls, e0, e1;

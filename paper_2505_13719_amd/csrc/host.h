@@ -47,6 +47,10 @@ struct HostProblem {
   int32_t rk = 0, nlc = 0;
   std::vector<double> Kc, Dc;
   std::vector<int32_t> lc_con, lc_off, lc_doff, lc_of_con;
+  // coded-diffraction constraints (Section 5.4) on the real form: L masks of
+  // n_c = n / 2 complex entries, interleaved (re, im), pattern-major
+  int32_t cdp_L = 0, cdp_nc = 0;
+  std::vector<double> cdp_d;
   std::vector<double> b;
   double b_l1 = 0.0, c_l1 = 0.0;
   // tiles (row ranges) and their pair-stream choices; the schedule's two
@@ -112,6 +116,7 @@ struct PendingOp {
   OpCode code = OP_NONE;
   int R = 0, R2 = 0;        // bucket (destination) and source bucket
   int xrole = 0, msel = -1, wT = 0, wyp = 0, zsel = 0;
+  int rlive = 0;            // columns of the operands that can be nonzero (<= R)
   int src = 0, dst = 0;
   const double *ext = nullptr;
   int ext_r = 0;
@@ -126,6 +131,7 @@ struct PendingOp {
 };
 
 struct Pool;
+struct CdpFft;  // FFT plans of a coded-diffraction instance (engine.cpp)
 
 // per-instance solver state (one HALLaR solve)
 struct Slot {
@@ -150,6 +156,7 @@ struct Slot {
   // buffer bookkeeping
   std::vector<int> free_bufs;
   int cur_R = 0;            // bucket of live U-like buffers
+  int cur_r = 1;            // columns of the iterate (the rest of the bucket is zero)
   InstParams prm{};
   const double *U0ext = nullptr;  // device FP64 U0
   int U0r = 0;
@@ -159,6 +166,7 @@ struct Slot {
   double t_start = 0.0;
   uint64_t seed = 0;
   std::string err;
+  CdpFft *fft = nullptr;    // owned; released by slot_unload
 };
 
 }  // namespace hl

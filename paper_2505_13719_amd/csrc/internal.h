@@ -169,6 +169,17 @@ struct InstDev {
   double *lc_v;      // rk: K^T v for a vector v
   double *lc_zv;     // rk: blockdiag(y''_l D_q) K^T v (added by the Lanczos SpMV)
   double *lc_Tv;     // nlc: (K_q^T v)^T D_q (K_q^T v) (Frank-Wolfe step size)
+  // coded-diffraction constraints (Section 5.4) on the real form, n = 2 nc:
+  // L masks d (nc complex each); spectra S of d_l * u_c, transform
+  // (l R + c) contiguous (the FFTs' batch order), and their scaled copy S2;
+  // cdp_T[l nc + k] = sum_c |S|^2 / nc (the constraint values); cdp_W[z] the
+  // adjoint's n x R block added by the SpMM epilogue (z the Z-slot);
+  // cdp_wv / cdp_Tv the Lanczos and Frank-Wolfe vector forms
+  int32_t cdp_L, cdp_nc;
+  const double2 *cdp_d;
+  double2 *cdp_S, *cdp_S2;
+  double *cdp_T, *cdp_Tv, *cdp_wv;
+  double *cdp_W[2];
 };
 
 // Reductions of the constraints' low-rank parts (k_lc_red): Y = K^T X and

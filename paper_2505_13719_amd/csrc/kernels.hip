@@ -448,6 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_constraints(const int32_t *__rest
       const int q = I.lc_of_con[l];
       if (q >= 0) t += I.lc_T[q];  // + K_l D_l K_l^T . U U^T (Algorithm 3)
     }
+    if (I.cdp_L > 0) t += I.cdp_T[l];  // coded-diffraction constraint value
     const double r = t - I.b[l];
     const double y = I.p[l] + P.beta * r;
     acc[0] = I.p[l] * r;
@@ -621,6 +622,12 @@ __device__ __forceinline__ void spmm_epi_apply(const InstDev &I, const InstParam
 #pragma unroll
       for (int e = 0; e < NC; ++e) w[e] += kv * Zc[(size_t)k * R_MAX + e];
     }
+  }
+  if (I.cdp_L > 0) {
+    // coded-diffraction constraints: their adjoint block, formed by the FFTs
+    const double *__restrict__ Wc = I.cdp_W[a.zsel] + (size_t)i * R + ch * NC;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) w[e] += Wc[e];
   }
   const size_t off = (size_t)i * R + ch * NC;
   if (MODE == SP_PLAIN) {
@@ -1330,6 +1337,7 @@ __global__ __launch_bounds__(BLOCK) void k_fw_den_gen(const int32_t *__restrict_
       const int q = I.lc_of_con[l];
       if (q >= 0) t += I.lc_Tv[q];
     }
+    if (I.cdp_L > 0) t += I.cdp_Tv[l];
     I.Ty[l] = t;
     const double d = I.TY[l] - P.tau2 * t;
     acc[0] = d * d;
@@ -1496,6 +1504,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
         const double *Kc = I.Kc64 + (size_t)i * I.rk;
         for (int k = 0; k < I.rk; ++k) w += Kc[k] * I.lc_zv[k];
       }
+      if (I.cdp_L > 0) w += I.cdp_wv[i];  // coded-diffraction part of G v
       // shifted three-term form: the Gram-Schmidt dots then see only the
       // small remainder, so the DGKS test can skip the second pass (the
       // host adds the shift and beta back into the projected matrix)
@@ -2414,6 +2423,130 @@ void op_lc_red(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
   LcArgs a{mode, R, zsel, mult};
   hipLaunchKernelGGL(k_lc_red, dim3(ni), dim3(RBLOCK), 0, s, ilist, d, a);
 }
+// ---------------------------------------------------------------------------
+// Coded-diffraction constraints (Section 5.4, eq. phase retrieval SDP) on the
+// real form, n = 2 nc: constraint l nc + k is sum_c |(F (d_l * u_c))_k|^2
+// with u_c = X[0:nc, c] + i X[nc:n, c] and F the unitary DFT; the adjoint
+// block is sum_l conj(d_l) * F^H (y_l * F (d_l * u_c)), split back into
+// real and imaginary rows.  The transforms run in rocFFT, unnormalised both
+// ways; the 1/nc of the unitary pair is applied by k_cdp_abs2 / k_cdp_scale.
+// Launched per instance (the instance's FFT plans are its own).
+// ---------------------------------------------------------------------------
+// S[(l Rc + c) nc + j] = d_l[j] u_c[j] for the first Rc columns (the ones
+// that can be nonzero: the iterate's rank; the rest of the bucket's R are
+// zero).  vsrc 0: role xrole, rows of stride R; 1: the Lanczos vector v_j
+// (zeros once the instance takes no more steps); 2: the Ritz vector lzv
+// (R = Rc = 1 for both vector forms).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_cdp_pack(const InstDev *__restrict__ insts, int s, int xrole, int vsrc,
+                                                    int R, int Rc) {
+  const InstDev &I = insts[s];
+  const InstParams &P = *I.prm;
+  const int nc = I.cdp_nc;
+  const size_t total = (size_t)I.cdp_L * Rc * nc;
+  const bool idle = vsrc == 1 && P.lz_steps <= 0;
+  const T *__restrict__ X = vsrc == 0 ? role_ptr<T>(I, P, xrole) : nullptr;
+  const double *__restrict__ v = vsrc == 1 ? lz_basis(I, P) + (size_t)P.lz_j * I.n : I.lzv;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = e / nc;
+    const int j = (int)(e - t * nc), c = (int)(t % Rc), l = (int)(t / Rc);
+    double re = 0.0, im = 0.0;
+    if (!idle) {
+      if (vsrc == 0) {
+        re = (double)X[(size_t)j * R + c];
+        im = (double)X[(size_t)(nc + j) * R + c];
+      } else {
+        re = v[j];
+        im = v[nc + j];
+      }
+    }
+    const double2 d = I.cdp_d[(size_t)l * nc + j];
+    I.cdp_S[e] = make_double2(d.x * re - d.y * im, d.x * im + d.y * re);
+  }
+}
+
+// out[l nc + k] = sum_c |S[(l Rc + c) nc + k]|^2 / nc, c in column order
+// (out 0: the constraint values cdp_T; 1: the Frank-Wolfe vector's cdp_Tv)
+__global__ __launch_bounds__(BLOCK) void k_cdp_abs2(const InstDev *__restrict__ insts, int s, int Rc, int out) {
+  const InstDev &I = insts[s];
+  const int nc = I.cdp_nc;
+  const size_t total = (size_t)I.cdp_L * nc;
+  double *__restrict__ o = out ? I.cdp_Tv : I.cdp_T;
+  const double inv = 1.0 / (double)nc;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t l = e / nc, k = e - l * nc;
+    const double2 *__restrict__ S = I.cdp_S + l * Rc * nc + k;
+    double acc = 0.0;
+    for (int c = 0; c < Rc; ++c) {
+      const double2 z = S[(size_t)c * nc];
+      acc += z.x * z.x + z.y * z.y;
+    }
+    o[e] = acc * inv;
+  }
+}
+
+// S2 = S * y_{l nc + k} / nc with the multipliers y (null: the instance's y')
+__global__ __launch_bounds__(BLOCK) void k_cdp_scale(const InstDev *__restrict__ insts, int s, int Rc,
+                                                     const double *__restrict__ mult) {
+  const InstDev &I = insts[s];
+  const int nc = I.cdp_nc;
+  const size_t total = (size_t)I.cdp_L * Rc * nc;
+  const double *__restrict__ y = mult ? mult : I.yp;
+  const double inv = 1.0 / (double)nc;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = e / nc, k = e - t * nc, l = t / Rc;
+    const double f = y[l * nc + k] * inv;
+    const double2 z = I.cdp_S[e];
+    I.cdp_S2[e] = make_double2(z.x * f, z.y * f);
+  }
+}
+
+// sum_l conj(d_l[j]) S2[(l Rc + c) nc + j], l in order, into row j (real
+// part) and row nc + j (imaginary part), column c < Rc of the adjoint block;
+// columns Rc..R-1 are zero (vec 0: cdp_W[zsel], rows of stride R; vec 1: the
+// Lanczos vector's cdp_wv, R = Rc = 1)
+__global__ __launch_bounds__(BLOCK) void k_cdp_gather(const InstDev *__restrict__ insts, int s, int R, int Rc,
+                                                      int zsel, int vec) {
+  const InstDev &I = insts[s];
+  const int nc = I.cdp_nc, L = I.cdp_L;
+  const size_t total = (size_t)R * nc;
+  double *__restrict__ W = vec ? I.cdp_wv : I.cdp_W[zsel];
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = e / nc, j = e - c * nc;
+    double re = 0.0, im = 0.0;
+    if ((int)c < Rc)
+      for (int l = 0; l < L; ++l) {
+        const double2 d = I.cdp_d[(size_t)l * nc + j];
+        const double2 z = I.cdp_S2[((size_t)l * Rc + c) * nc + j];
+        re += d.x * z.x + d.y * z.y;
+        im += d.x * z.y - d.y * z.x;
+      }
+    W[j * R + c] = re;
+    W[(nc + j) * R + c] = im;
+  }
+}
+
+static unsigned cdp_grid(size_t total) {
+  const size_t g = (total + BLOCK - 1) / BLOCK;
+  return (unsigned)std::max<size_t>(1, std::min<size_t>(g, 16384));
+}
+void op_cdp_pack(int prec, hipStream_t st, const InstDev *d, int s, int xrole, int vsrc, int R, int Rc,
+                 size_t total) {
+  if (is64(prec) || vsrc != 0)
+    hipLaunchKernelGGL(k_cdp_pack<double>, dim3(cdp_grid(total)), dim3(BLOCK), 0, st, d, s, xrole, vsrc, R, Rc);
+  else
+    hipLaunchKernelGGL(k_cdp_pack<float>, dim3(cdp_grid(total)), dim3(BLOCK), 0, st, d, s, xrole, vsrc, R, Rc);
+}
+void op_cdp_abs2(hipStream_t st, const InstDev *d, int s, int Rc, int out, size_t total) {
+  hipLaunchKernelGGL(k_cdp_abs2, dim3(cdp_grid(total)), dim3(BLOCK), 0, st, d, s, Rc, out);
+}
+void op_cdp_scale(hipStream_t st, const InstDev *d, int s, int Rc, const double *mult, size_t total) {
+  hipLaunchKernelGGL(k_cdp_scale, dim3(cdp_grid(total)), dim3(BLOCK), 0, st, d, s, Rc, mult);
+}
+void op_cdp_gather(hipStream_t st, const InstDev *d, int s, int R, int Rc, int zsel, int vec, size_t total) {
+  hipLaunchKernelGGL(k_cdp_gather, dim3(cdp_grid(total)), dim3(BLOCK), 0, st, d, s, R, Rc, zsel, vec);
+}
+
 void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v) {
   hipLaunchKernelGGL(k_put_params, dim3(1), dim3(64), 0, s, dst, v);
 }

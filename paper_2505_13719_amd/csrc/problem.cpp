@@ -47,6 +47,30 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
     if (p->lr_rank[t] < 1) return "lr_rank must be >= 1";
     if (p->lr_con[t] > 0) has_lc = true;
   }
+  if (p->cdp_patterns < 0) return "cdp_patterns < 0";
+  if (p->cdp_patterns > 0) {
+    const int64_t L = p->cdp_patterns;
+    if (!p->cdp_masks) return "cdp_masks is NULL";
+    if (n % 2 != 0) return "coded-diffraction problems need an even n (the real form of n/2 complex entries)";
+    if ((int64_t)m != L * (n / 2)) return "coded-diffraction problems need m = cdp_patterns * n / 2";
+    if (p->n_lowrank > 0) {
+      *code = HALLAR_E_UNSUPPORTED;
+      return "coded-diffraction constraints cannot be combined with low-rank terms";
+    }
+    for (int64_t k = 0; k < p->nnz; ++k)
+      if (p->con[k] != 0) {
+        *code = HALLAR_E_UNSUPPORTED;
+        return "coded-diffraction problems take sparse entries on the objective only";
+      }
+    hp.cdp_L = (int32_t)L;
+    hp.cdp_nc = n / 2;
+    hp.cdp_d.assign(p->cdp_masks, p->cdp_masks + 2 * L * (n / 2));
+    for (double v : hp.cdp_d)
+      if (!std::isfinite(v)) {
+        *code = HALLAR_E_NUMERICAL;
+        return "cdp_masks has NaN/Inf";
+      }
+  }
   std::vector<Ent> e((size_t)p->nnz);
   for (int64_t k = 0; k < p->nnz; ++k) {
     const int32_t i = p->row[k], j = p->col[k], l = p->con[k];
@@ -115,7 +139,7 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
   for (int l = 0; l < m; ++l)
     if (ccount[l] != 1) direct = false;
   // a constraint with a low-rank part sums more than its pairs
-  if (has_lc) direct = false;
+  if (has_lc || hp.cdp_L > 0) direct = false;
   for (int i = 0; i < n; ++i) hp.rowptr_u[i + 1] += hp.rowptr_u[i];
   hp.direct = direct;
   hp.has_c = has_c;

@@ -29,7 +29,7 @@ class hallar_problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("trace_bound", C.c_double), ("nnz", C.c_int64),
                 ("row", i32p), ("col", i32p), ("con", i32p), ("val", f64p),
                 ("n_lowrank", C.c_int32), ("lr_con", i32p), ("lr_rank", i32p), ("K_off", i64p), ("D_off", i64p),
-                ("K", f64p), ("D", f64p), ("b", f64p)]
+                ("K", f64p), ("D", f64p), ("b", f64p), ("cdp_patterns", C.c_int32), ("cdp_masks", f64p)]
 
 
 class hallar_options(C.Structure):
@@ -172,6 +172,12 @@ class _ProblemArrays:
             p.D_off = self.D_off.ctypes.data_as(i64p)
             p.K = self.K.ctypes.data_as(f64p)
             p.D = self.D.ctypes.data_as(f64p)
+        masks = getattr(prob, "cdp_masks", None)
+        if masks is not None:
+            # complex masks as interleaved (re, im) doubles
+            self.cdp = np.ascontiguousarray(masks, dtype=np.complex128).view(np.float64).reshape(-1)
+            p.cdp_patterns = int(masks.shape[0])
+            p.cdp_masks = self.cdp.ctypes.data_as(f64p)
         self.c = p
 
 
@@ -394,7 +400,8 @@ def hallar_pool_usage(pool):
     return u.value, b.value
 
 
-KERNEL_CLASSES = ["sddmm", "spmm", "lanczos_spmv", "lanczos_reorth", "vector", "reduce", "other", "sddmm_spmm"]
+KERNEL_CLASSES = ["sddmm", "spmm", "lanczos_spmv", "lanczos_reorth", "vector", "reduce", "other", "sddmm_spmm",
+                  "cdp"]
 
 
 def _profile(fn, obj, reset):

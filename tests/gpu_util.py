@@ -62,3 +62,26 @@ def entrywise(x, ref, terms, tol, u):
 
 
 U32, U64 = 2.0 ** -24, 2.0 ** -53
+
+
+def cdp_terms(prob, U, ptil=None):
+    """Error scales of the coded-diffraction operators (FFT rounding is
+    normwise: a unitary transform of v errs by O(u log n) ||v||_2 in every
+    entry).  For T: per constraint (l, k), 2 sum_c ||d_l u_c||_2 (|S_lkc| +
+    ||d_l u_c||_2) with S the spectra; for W = A*(p~)U: per entry,
+    sum_l |d_lj| max|y_l| ||d_l u_c||_2 plus the sparse part |C||U|."""
+    L, nc = prob.cdp_masks.shape
+    U = np.asarray(U, np.float64).reshape(prob.n, -1)
+    Uc = U[:nc] + 1j * U[nc:]
+    V = prob.cdp_masks[:, :, None] * Uc[None]
+    nv = np.linalg.norm(V, axis=1)                           # (L, r)
+    S = np.fft.fft(V, axis=1, norm="ortho")
+    tT = np.zeros(prob.m + 1)
+    tT[0] = float((U * U).sum())
+    tT[1:] = (2.0 * nv[:, None, :] * (np.abs(S) + nv[:, None, :])).sum(axis=2).reshape(-1)
+    if ptil is None:
+        return tT
+    y = np.abs(np.asarray(ptil)[1:]).reshape(L, nc).max(axis=1)      # (L,)
+    half = (np.abs(prob.cdp_masks)[:, :, None] * (y[:, None] * nv)[:, None, :]).sum(axis=0)  # (nc, r)
+    tW = np.vstack([half, half]) + abs(ptil[0]) * np.abs(U)
+    return tT, tW

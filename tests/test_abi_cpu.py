@@ -103,3 +103,26 @@ def test_option_validation(field, value):
         H.hallar_create(si.random_hslr(8, 4, 0), H.FP64, o, stream=0)  # no device is touched
     assert e.value.status == 1
     assert field in str(e.value)
+
+
+def test_coded_diffraction_validation():
+    """Coded-diffraction problems (Section 5.4, real form): the shapes are
+    checked and mixtures refused before any device work."""
+    p = si.phase_retrieval_cdp(12, 3, seed=1)
+    assert H.hallar_footprint(p) > 0
+    assert H.hallar_inspect(p)["direct"] == 0
+    q = si.phase_retrieval_cdp(12, 3, seed=1)
+    q.m, q.b = q.m - 1, q.b[:-1]                      # m != L n_c
+    _bad(q, 1)
+    q = si.phase_retrieval_cdp(12, 3, seed=1)
+    q.n = q.n + 1                                      # odd n
+    _bad(q, 1)
+    q = si.phase_retrieval_cdp(12, 3, seed=1)
+    q.con = q.con.copy(); q.con[0] = 1                 # a sparse constraint entry
+    _bad(q, 2)
+    q = si.phase_retrieval_cdp(12, 3, seed=1)
+    q.lr_con, q.lr_K, q.lr_D = [0], [np.ones((q.n, 1))], [np.eye(1)]
+    _bad(q, 2)
+    q = si.phase_retrieval_cdp(12, 3, seed=1)
+    q.cdp_masks = q.cdp_masks.copy(); q.cdp_masks[1, 2] = np.nan
+    _bad(q, 9)

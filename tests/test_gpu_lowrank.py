@@ -158,3 +158,33 @@ def test_sdpa_dense_split_solve():
     assert res["status"] == "ok", res
     assert max(res["pinf"], res["gap"], res["dinf"]) <= 1e-6
     assert abs(res["pval"] - ref["pval"]) <= 1e-5 * (1.0 + abs(ref["pval"])), (res["pval"], ref["pval"])
+
+
+def test_lowrank_batch_equals_alone():
+    """Instances with low-rank constraint terms batched with a MaxCut
+    instance: every result is bit-identical to its solve alone (the batch's
+    views carry the low-rank parts' sizes)."""
+    d = dev()
+    rng = np.random.default_rng(6)
+    i, j = si.er_edges(200, 8.0 / 199, rng)
+    text, tr = random_sdpa_text(24, 8, seed=3)
+    probs = [si.phaselift_real(30, 180, seed=30), si.maxcut_problem(200, i, j, si.pm1_weights(i.size, rng)),
+             read_sdpa(text, 3.0 * tr)]
+    keys = ("status", "pval", "dval", "pinf", "gap", "dinf", "rank", "outer_iters", "n_fista_trials")
+    alone = []
+    for p in probs:
+        h = H.hallar_create(p, H.FP64, H.options(eps=1e-5))
+        try:
+            alone.append(H.hallar_solve(h, torch.tensor(si.gaussian_u0(p.n, 3), device=d)))
+        finally:
+            H.hallar_destroy(h)
+    hs = [H.hallar_create(p, H.FP64, H.options(eps=1e-5)) for p in probs]
+    try:
+        batch = H.hallar_solve_batch(hs, [torch.tensor(si.gaussian_u0(p.n, 3), device=d) for p in probs])
+    finally:
+        for h in hs:
+            H.hallar_destroy(h)
+    for a, b in zip(alone, batch):
+        assert a["status"] == "ok", a
+        for k in keys:
+            assert a[k] == b[k], (k, a[k], b[k])
