@@ -481,7 +481,7 @@ static void cdp_exec(Pool &P, CdpFft &F, int batch, bool forward, void *buf, hip
 static void cdp_forward(Pool &P, int s, hipStream_t st, int xrole, int vsrc, int R, int Rc, int out) {
   Slot &S = *P.slots[s];
   const size_t L = S.hp.cdp_L, nc = S.hp.cdp_nc;
-  op_cdp_pack(P.prec, st, P.d_insts, s, xrole, vsrc, R, Rc, L * Rc * nc);
+  op_cdp_pack(P.prec, st, P.d_insts, s, xrole, vsrc, R, Rc, L * Rc * nc, (int)nc);
   cdp_exec(P, *S.fft, (int)(L * Rc), true, S.dev.cdp_S, st);
   if (out >= 0) op_cdp_abs2(st, P.d_insts, s, Rc, out, L * nc);
 }
@@ -495,7 +495,7 @@ static void cdp_adjoint(Pool &P, int s, hipStream_t st, int R, int Rc, int zsel,
   const size_t L = S.hp.cdp_L, nc = S.hp.cdp_nc;
   op_cdp_scale(st, P.d_insts, s, Rc, mult, L * Rc * nc);
   cdp_exec(P, *S.fft, (int)(L * Rc), false, S.dev.cdp_S2, st);
-  op_cdp_gather(st, P.d_insts, s, R, Rc, zsel, vec, (size_t)R * nc);
+  op_cdp_gather(st, P.d_insts, s, R, Rc, zsel, vec, (size_t)R * nc, (int)nc);
 }
 
 hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {

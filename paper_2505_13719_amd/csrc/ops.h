@@ -16,10 +16,10 @@ enum RedOpH : int {
 // coded-diffraction constraints (Section 5.4): per-instance launches around
 // the instance's FFTs; total = elements of the launch's index space
 void op_cdp_pack(int prec, hipStream_t st, const InstDev *d, int s, int xrole, int vsrc, int R, int Rc,
-                 size_t total);
+                 size_t total, int nc);
 void op_cdp_abs2(hipStream_t st, const InstDev *d, int s, int Rc, int out, size_t total);
 void op_cdp_scale(hipStream_t st, const InstDev *d, int s, int Rc, const double *mult, size_t total);
-void op_cdp_gather(hipStream_t st, const InstDev *d, int s, int R, int Rc, int zsel, int vec, size_t total);
+void op_cdp_gather(hipStream_t st, const InstDev *d, int s, int R, int Rc, int zsel, int vec, size_t total, int nc);
 void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v);
 // Constraints' low-rank parts: partial K^T X per tile (vsrc 0: role xrole of
 // R columns; 1: the Lanczos vector being multiplied; 2: the Ritz vector),
