@@ -265,6 +265,27 @@ hallar_status hallar_solve(hallar_t h, const double *U0, int32_t r0, const doubl
  * ldu >= rank) and p (device double[m]); either may be NULL. */
 hallar_status hallar_get_solution(hallar_t h, double *U, int64_t ldu, double *p, void *stream);
 
+/* One record per outer iteration t of the last solve on the handle (Alg. 1,
+ * outer loop; the quantities of eq. termination2 after the multiplier update
+ * of that iteration, and the penalty it ran with). */
+typedef struct {
+  int32_t t;             /* outer iteration, 1-based */
+  int32_t rank;          /* columns of U after the iteration */
+  double beta;           /* penalty used in the iteration */
+  double pval, dval, theta;
+  double pinf, gap, dinf;/* relative errors of eq. termination2 */
+  double obj_bound;      /* |pval - dval| + |p^T (A(X) - b)| */
+  double seconds;        /* since the solve started */
+  int64_t n_fista_trials, n_matvec, n_hlr_iters; /* cumulative */
+} hallar_outer_record;
+
+/* Copy the last solve's outer-iteration records (a trace of the run) into
+ * out[0 .. min(cap, total) - 1] (host); *total receives the number of
+ * records (= res.outer_iters for a solve that ended inside the loop).
+ * out may be NULL with cap = 0 to query the count.  Handles solved in a
+ * batch keep their own records. */
+hallar_status hallar_get_history(hallar_t h, hallar_outer_record *out, int32_t cap, int32_t *total);
+
 /* Batched solve: `count` handles of the same precision solved together;
  * their operator work runs in shared, segment-indexed kernel launches (one
  * launch covers the tiles of every instance that needs that kernel).  U0s

@@ -399,6 +399,16 @@ hallar_status hallar_get_solution(hallar_t h, double *U, int64_t ldu, double *p,
   return HALLAR_OK;
 }
 
+hallar_status hallar_get_history(hallar_t h, hallar_outer_record *out, int32_t cap, int32_t *total) {
+  if (!h || !h->P.slots[0]) return fail(h, HALLAR_E_INVALID, "bad handle");
+  if (!total || cap < 0 || (cap > 0 && !out)) return fail(h, HALLAR_E_INVALID, "total required; out required when cap > 0");
+  const std::vector<hallar_outer_record> &hist = h->P.slots[0]->history;
+  *total = (int32_t)hist.size();
+  const size_t k = std::min(hist.size(), (size_t)cap);
+  for (size_t i = 0; i < k; ++i) out[i] = hist[i];
+  return HALLAR_OK;
+}
+
 hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *const *U0s, hallar_result *results) {
   if (!hs || count < 1 || !results) return fail(nullptr, HALLAR_E_INVALID, "hs, count >= 1 and results required");
   const int prec = hs[0] ? hs[0]->prec : 0;
@@ -484,6 +494,7 @@ hallar_status hallar_solve_batch(hallar_t *hs, int32_t count, const double *cons
     src.final_r = v.final_r;
     src.cur_R = v.cur_R;
     src.result = v.result;
+    src.history = std::move(v.history);
     v.slab = nullptr;  // views: do not free
     v.fft = nullptr;
   }

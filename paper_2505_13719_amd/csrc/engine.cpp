@@ -1992,6 +1992,25 @@ static Task solve_main(Ctx c) {
       res.obj_bound = std::fabs(pval - dval) + std::fabs(ptr);
       return !o.obj_check || res.obj_bound <= o.eps * (1.0 + std::fabs(pval));
     };
+    // the iteration's record (after the certification below, if it ran)
+    auto record = [&]() {
+      hallar_outer_record rec{};
+      rec.t = t;
+      rec.rank = r;
+      rec.beta = beta;
+      rec.pval = pval;
+      rec.dval = dval;
+      rec.theta = theta;
+      rec.pinf = pinf;
+      rec.gap = gapr;
+      rec.dinf = dinf;
+      rec.obj_bound = std::fabs(pval - dval) + std::fabs(ptr);
+      rec.seconds = now_s() - t0;
+      rec.n_fista_trials = res.n_fista_trials;
+      rec.n_matvec = res.n_matvec;
+      rec.n_hlr_iters = res.n_hlr_iters;
+      S.history.push_back(rec);
+    };
     if (std::max(pinf, std::max(gapr, dinf)) <= o.eps) {
       // Certification: the Ritz value bounds lambda_min from above, and near
       // the optimum a warm-started run can settle on a member of the cluster
@@ -2012,10 +2031,12 @@ static Task solve_main(Ctx c) {
       }
       if (std::max(pinf, std::max(gapr, dinf)) <= o.eps && obj_ok()) {
         res.status = HALLAR_OK;
+        record();
         break;
       }
     }
     obj_ok();
+    record();
     if (now_s() - t0 > o.time_limit) {
       res.status = HALLAR_E_TIME_LIMIT;
       break;
@@ -2057,6 +2078,7 @@ void slot_start_solve(Pool &P, int s) {
     S.prm.tau2 = tau2;
   }
   S.lz_sigma = 0.0;
+  S.history.clear();
   S.free_bufs.clear();
   for (int q = NBUF - 1; q >= 0; --q) S.free_bufs.push_back(q);
   if (S.task) delete S.task;

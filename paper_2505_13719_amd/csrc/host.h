@@ -167,6 +167,7 @@ struct Slot {
   uint64_t seed = 0;
   std::string err;
   CdpFft *fft = nullptr;    // owned; released by slot_unload
+  std::vector<hallar_outer_record> history;  // one record per outer iteration of the solve
 };
 
 }  // namespace hl

@@ -61,12 +61,20 @@ class hallar_result(C.Structure):
         return d
 
 
+class hallar_outer_record(C.Structure):
+    _fields_ = [("t", C.c_int32), ("rank", C.c_int32), ("beta", C.c_double), ("pval", C.c_double),
+                ("dval", C.c_double), ("theta", C.c_double), ("pinf", C.c_double), ("gap", C.c_double),
+                ("dinf", C.c_double), ("obj_bound", C.c_double), ("seconds", C.c_double),
+                ("n_fista_trials", C.c_int64), ("n_matvec", C.c_int64), ("n_hlr_iters", C.c_int64)]
+
+
 class hallar_eig_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("residual", C.c_double)]
 
 
 EXPORTS = ["hallar_default_options", "hallar_create", "hallar_destroy", "hallar_last_error", "hallar_describe",
            "hallar_eval_AUUt", "hallar_eval_AUUt_noalloc", "hallar_adjoint_spmm", "hallar_min_eig", "hallar_solve", "hallar_get_solution",
+           "hallar_get_history",
            "hallar_solve_batch", "hallar_footprint", "hallar_pool_create", "hallar_pool_destroy",
            "hallar_pool_admit", "hallar_pool_step", "hallar_pool_poll", "hallar_pool_usage", "hallar_profile",
            "hallar_pool_profile", "hallar_schedule", "hallar_inspect"]
@@ -97,6 +105,7 @@ def load(path: str = LIB_PATH):
     L.hallar_min_eig.argtypes = [vp, vp, vp, C.c_double, C.c_int32, f64p, vp, C.POINTER(hallar_eig_info), vp]
     L.hallar_solve.argtypes = [vp, vp, C.c_int32, vp, C.POINTER(hallar_result)]
     L.hallar_get_solution.argtypes = [vp, vp, C.c_int64, vp, vp]
+    L.hallar_get_history.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int32)]
     L.hallar_solve_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp), C.POINTER(hallar_result)]
     L.hallar_footprint.argtypes = [C.POINTER(hallar_problem), C.c_int, C.POINTER(hallar_options), C.POINTER(C.c_size_t)]
     L.hallar_inspect.argtypes = [C.POINTER(hallar_problem), C.POINTER(hallar_structure), i64p, C.c_int64]
@@ -311,6 +320,15 @@ def hallar_get_solution(h, U=None, p=None, stream=None):
         _need(p, "p", torch.float64, numel=h.m)
     ld = 0 if U is None else U.stride(0)
     return _check(load().hallar_get_solution(h, _ptr(U), ld, _ptr(p), _stream(stream)), h)
+
+
+def hallar_get_history(h):
+    """The last solve's outer-iteration records, as a list of dicts."""
+    n = C.c_int32(0)
+    _check(load().hallar_get_history(h, None, 0, C.byref(n)), h)
+    arr = (hallar_outer_record * max(n.value, 1))()
+    _check(load().hallar_get_history(h, arr, n.value, C.byref(n)), h)
+    return [{k: getattr(arr[i], k) for k, _ in hallar_outer_record._fields_} for i in range(n.value)]
 
 
 def hallar_solve_batch(handles, U0s=None):
