@@ -870,10 +870,14 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
   static_assert(G <= 2, "the fused trial kernel takes narrow rows");
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
-  // entries in flight per lane: four for one-chunk rows, two for two-chunk
-  // rows (measured on matrix completion: FP32 rank 4 260 / 272 us with four /
-  // two, FP64 rank 4 351 / 316 us; eight costs registers and occupancy)
-  constexpr int UN = G == 1 ? 4 : 2;
+  // entries per step and lane: two for one-chunk rows, one for two-chunk
+  // rows, with the next step's index loads issued before this step's rows
+  // are gathered (software pipeline).  Measured on matrix completion rank 4:
+  // FP64 340 -> 300 us and FP32 252 -> 217 us against the unpipelined walk
+  // with two / four entries in flight; the pipelined walk with twice the
+  // entries per step is slower (302 / 224 us: registers), with four
+  // slower still (329 us FP64)
+  constexpr int UN = G == 1 ? 2 : 1;
   __shared__ int32_t s_ru[TILE_MAX_ROWS + 1], s_rl[TILE_MAX_ROWS + 1];
   const Tile tl = tiles[tile_index()];
   const InstDev &I = insts[tl.inst];
@@ -912,28 +916,37 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
     double w[NC];
 #pragma unroll
     for (int e = 0; e < NC; ++e) w[e] = 0.0;
-    for (int q = strm; q < cnt; q += S * UN) {
-      Chunk<T> x[UN];
-      double2 pb[UN];
-      int col[UN], lk[UN];
+    // software pipeline: the next step's columns and {p_l, b_l} are loaded
+    // while this step's factor rows are gathered
+    double2 pb[UN], pbn[UN];
+    int col[UN], lk[UN], coln[UN], lkn[UN];
+    auto idx_load = [&](int q0, int (&cl)[UN], double2 (&pv)[UN], int (&lv)[UN]) {
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
-        const int idx = q + u * S;
-        lk[u] = 0;
+        const int idx = q0 + u * S;
+        lv[u] = 0;
+        cl[u] = i;
         if (idx < cnt) {
           if (idx < cu) {
             const int k = ku + idx;
-            col[u] = ldg(I.col_u + k);
-            if (!I.con_rule) lk[u] = ldg(I.pcon + k);
-            pb[u] = ldg(upb + k);
+            cl[u] = ldg(I.col_u + k);
+            if (!I.con_rule) lv[u] = ldg(I.pcon + k);
+            pv[u] = ldg(upb + k);
           } else {
             const int e = kl + idx - cu;
-            col[u] = ldg(I.col_l + e);
-            pb[u] = ldg(low_pb + e);
+            cl[u] = ldg(I.col_l + e);
+            pv[u] = ldg(low_pb + e);
           }
-          x[u] = ldc(X + (size_t)col[u] * R + ch * NC);
         }
       }
+    };
+    idx_load(strm, col, pb, lk);
+    for (int q = strm; q < cnt; q += S * UN) {
+      Chunk<T> x[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+        if (q + u * S < cnt) x[u] = ldc(X + (size_t)col[u] * R + ch * NC);
+      if (q + S * UN < cnt) idx_load(q + S * UN, coln, pbn, lkn);
       // lanes of a G-group share idx: the butterfly stays inside lanes that
       // take the branch together, and one lane of the group adds the SDDMM
       // sums
@@ -966,6 +979,12 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
         const double mt = (double)(T)mv;
 #pragma unroll
         for (int e = 0; e < NC; ++e) w[e] += mt * (double)x[u].v[e];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        col[u] = coln[u];
+        lk[u] = lkn[u];
+        pb[u] = pbn[u];
       }
     }
     for (int o = TS / 2; o >= G; o >>= 1) {
