@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HAMMING_D = 20
 
 
 def workload(name):
@@ -50,12 +51,13 @@ def workload(name):
         return si.theta_er(50_000, 10.0, seed=3), H.FP32_MIXED, dict(rank_cap=64), \
             {"workload": "theta_er_50000_deg10", "n": 50_000, "rank_cap": 64}
     if name == "hamming":
-        # Table tab:reduced_hamming_graphs: H(20, 2), theta = n/2
-        d = 20
+        # Table tab:reduced_hamming_graphs: H(d, 2), theta = n/2 (d = 20 by
+        # default; the table goes to d = 23)
+        d = HAMMING_D
         n = 1 << d
-        prob = si.theta_problem(n, *si.hypercube_edges(d), name="hamming_20_2")
+        prob = si.theta_problem(n, *si.hypercube_edges(d), name=f"hamming_{d}_2")
         prob.meta["optimum"] = -n / 2
-        return prob, H.FP64, {}, {"workload": "theta_hamming_H(20,2)", "n": n, "m": int(prob.m)}
+        return prob, H.FP64, {}, {"workload": f"theta_hamming_H({d},2)", "n": n, "m": int(prob.m)}
     if name == "phase":
         # complex phase retrieval from 12 coded diffraction patterns (Section
         # 5.4, the table's n = 100,000, m = 1,200,000 row), on the real form;
@@ -506,6 +508,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--hamming-d", type=int, default=20, help="d of H(d, 2) for --workload hamming (10..23)")
     ap.add_argument("--workload", default="mc",
                     choices=["torus", "er800", "theta", "mc", "hamming", "phase", "served", "ops"])
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
@@ -536,6 +539,11 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    global HAMMING_D
+    if not 10 <= args.hamming_d <= 23:
+        print("--hamming-d takes 10..23 (the graphs of the table)", file=sys.stderr)
+        sys.exit(2)
+    HAMMING_D = args.hamming_d
     if args.workload == "ops":
         out = bench_ops(args)
     else:
