@@ -5,7 +5,7 @@ bipartite, hence perfect, so theta = alpha = n / 2 exactly (n = 2^d).
 
 The solve's objective must sit within 1e-5 relative of -n/2 with relative
 gap, infeasibility and dual infeasibility <= 1e-5, in FP64 up to
-d = 18 (n = 262,144, 2,359,296 edge constraints) and in FP32-mixed; its
+d = 21 (n = 2,097,152, 22,020,096 edge constraints) and in FP32-mixed; its
 primal side is recomputed without the GPU from the returned U (the oracle's
 A~(UU^T)), and for the sizes where scipy's eigsh finishes in seconds, the
 dual value from the exact lambda_min of C + A*(p) certifies the result from
@@ -39,7 +39,7 @@ def _solve(d, prec):
 
 
 @pytest.mark.parametrize("d,prec", [(10, H.FP64), (12, H.FP64), (14, H.FP64), (16, H.FP64), (18, H.FP64),
-                                    (12, H.FP32_MIXED), (16, H.FP32_MIXED)])
+                                    (21, H.FP64), (12, H.FP32_MIXED), (16, H.FP32_MIXED)])
 def test_theta_hamming_is_half_n(d, prec):
     prob, res, U, p = _solve(d, prec)
     n = prob.n
