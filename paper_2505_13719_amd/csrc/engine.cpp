@@ -463,15 +463,20 @@ static hallar_status cdp_plans(const HostProblem &h, int prec, int Rcap, CdpFft 
 }
 
 // one batch of in-place transforms on the instance's stream
+// (a failure is recorded in P.launch_err and ends the round with an error)
 static void cdp_exec(Pool &P, CdpFft &F, int batch, bool forward, void *buf, hipStream_t st) {
+  if (P.launch_err != HALLAR_OK) return;
   const CdpFft::Pair *pr = cdp_plan(F, batch, P.err);
   if (!pr) {
-    std::fprintf(stderr, "[hallar] %s\n", P.err.c_str());
+    P.launch_err = HALLAR_E_HIP;
     return;
   }
-  (void)rocfft_execution_info_set_stream(F.info, st);
   void *io[1] = {buf};
-  (void)rocfft_execute(forward ? pr->fwd : pr->inv, io, nullptr, F.info);
+  if (rocfft_execution_info_set_stream(F.info, st) != rocfft_status_success ||
+      rocfft_execute(forward ? pr->fwd : pr->inv, io, nullptr, F.info) != rocfft_status_success) {
+    P.err = "rocfft_execute failed (batch " + std::to_string(batch) + ")";
+    P.launch_err = HALLAR_E_HIP;
+  }
 }
 
 // Spectra F (d_l * u_c) of the first Rc columns of role xrole (vsrc 0, rows
@@ -1258,6 +1263,11 @@ static hallar_status run_round(Pool &P, bool &did_work) {
         HL_TRY(hipEventRecord(P.ev_join[q - 1], P.side[q - 1]), "join");
         HL_TRY(hipStreamWaitEvent(ms, P.ev_join[q - 1], 0), "join wait");
       }
+    }
+    if (P.launch_err != HALLAR_OK) {
+      const hallar_status e = P.launch_err;
+      P.launch_err = HALLAR_OK;
+      return e;
     }
     return HALLAR_OK;
   };
@@ -2173,7 +2183,14 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
     op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
     op_lc_red(st, IL, 1, D, LC_Y_T, R, 0);
   }
-  if (S.hp.cdp_L > 0) cdp_forward(P, s, st, RU, 0, R, r, 0);
+  if (S.hp.cdp_L > 0) {
+    cdp_forward(P, s, st, RU, 0, R, r, 0);
+    if (P.launch_err != HALLAR_OK) {
+      const hallar_status e = P.launch_err;
+      P.launch_err = HALLAR_OK;
+      return e;
+    }
+  }
   if (!S.hp.direct) op_gen_constraints(P.prec, st, IL, 1, S.hp.m, D, 1);
   op_reduce(st, IL, 1, D, RDH_EVAL, 0, R, 0);
   HL_TRY(hipMemcpyAsync(T, &P.d_res[s].v[S_T0], sizeof(double), hipMemcpyDeviceToDevice, st), "T0");
@@ -2308,6 +2325,11 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
     // the coded-diffraction block D_l^H F^H (p_l * F D_l U)
     cdp_forward(P, s, st, RU, 0, R, r, -1);
     cdp_adjoint(P, s, st, R, r, 0, 0, p);
+    if (P.launch_err != HALLAR_OK) {
+      const hallar_status e = P.launch_err;
+      P.launch_err = HALLAR_OK;
+      return e;
+    }
   }
   op_spmm(P.prec, R, st, T_, nt, D, RU, 0, 0, RU2, SPM_PLAIN);
   if (!w_direct) op_unpack_op(P.prec, R, st, T_, nt, D, W, r, ldw, RU2);

@@ -99,6 +99,7 @@ struct Pool {
   int64_t rounds = 0;
   std::string err;
   hallar_status fatal = HALLAR_OK;
+  hallar_status launch_err = HALLAR_OK;  // set by a launch helper that failed inside a round (err says why)
   // profiling (opts.profile)
   bool profile = false;
   int prof_level = 0;  // 1: every kernel class, 2: the sparse streaming classes only
