@@ -318,7 +318,10 @@ hallar_status hallar_inspect(const hallar_problem *prob, hallar_structure *out, 
 /* ---- serving pool: continuous batching with HBM-footprint admission ---- */
 
 /* Device bytes an instance would hold in a pool (problem data + solver
- * workspaces).  Deterministic: the pool admits by exactly this number. */
+ * workspaces).  Deterministic: the pool admits by exactly this number.  Not
+ * included: the FFT plans of a coded-diffraction instance and their work
+ * buffer, which rocFFT sizes when the plans are made (allocated outside the
+ * pool's budget, up to about the spectra of L x the column capacity). */
 hallar_status hallar_footprint(const hallar_problem *prob, hallar_precision prec,
                                const hallar_options *opts, size_t *bytes);
 
