@@ -67,6 +67,13 @@ def workload(name):
         prob.meta["optimum"] = prob.tau2
         return prob, H.FP64, {}, {"workload": "phase_retrieval_cdp_n1e5_L12", "n_complex": nc, "n": 2 * nc,
                                   "m": 12 * nc}
+    if name == "lowrank":
+        # low-rank constraint terms (Section 3.2, eq. HSLR-rep-body) with
+        # about 3900 columns of K in all on n = 1e5 rows: the dense
+        # contraction K^T U of Algorithms 3 and 5 dominates the operators
+        prob = si.lowrank_constraints(100_000, 2900, seed=7)
+        rk = sum(K.shape[1] for l, K in zip(prob.lr_con, prob.lr_K) if l > 0)
+        return prob, H.FP64, {}, {"workload": "lowrank_constraints_n1e5_m2900", "n": prob.n, "m": prob.m, "rk": rk}
     if name == "mc":
         n1 = n2 = 100_000
         return si.mc_planted(n1, n2, 3, 20 * 3 * (n1 + n2), seed=4), H.FP64, dict(rank_cap=16), \
@@ -471,7 +478,7 @@ def bench_ops(args):
         prec = H.FP64 if args.precision == "fp64" else H.FP32_MIXED
     dt = torch.float64 if prec == H.FP64 else torch.float32
     dev = torch.device("cuda:0")
-    r = 4 if args.ops_instance == "mc" else 32
+    r = 32 if args.ops_instance == "torus" else 4
     h = H.hallar_create(prob, prec, H.options(eps=1e-5, profile=1, **kw))
     g = torch.Generator(device="cpu").manual_seed(0)
     U = (torch.randn((prob.n, r), generator=g, dtype=dt) / math.sqrt(r)).to(dev)
@@ -498,9 +505,16 @@ def bench_ops(args):
         out[name] = round(e0.elapsed_time(e1) * 1e3 / args.steps, 2)
         print(f"[bench] {name}: {out[name]} us/call", file=sys.stderr, flush=True)
     H.hallar_destroy(h)
-    return {"metric": "operator us/call", "config": dict(cfg, r=r, precision="fp64" if prec == H.FP64 else "fp32_mixed"),
-            "us_per_call": out,
-            "copy_gbs": round(2 * (1 << 30) / (out["copy_1GiB"] * 1e-6) / 1e9, 1)}
+    res = {"metric": "operator us/call", "config": dict(cfg, r=r, precision="fp64" if prec == H.FP64 else "fp32_mixed"),
+           "us_per_call": out,
+           "copy_gbs": round(2 * (1 << 30) / (out["copy_1GiB"] * 1e-6) / 1e9, 1)}
+    if "rk" in cfg:
+        # K (n x rk, operator type) read once per evaluation and once per
+        # adjoint: its rate against the HBM peak
+        kb = prob.n * cfg["rk"] * (8 if prec == H.FP64 else 4)
+        res["K_bytes"] = kb
+        res["K_gbs"] = {k: round(kb / (out[k] * 1e-6) / 1e9, 1) for k in ("eval_AUUt", "adjoint_spmm")}
+    return res
 
 
 def main():
@@ -518,7 +532,7 @@ def main():
                     help="HIP-event timing inside the timed solves: 2 = the sparse kernel classes only (default, "
                          "least overhead), 1 = every class, 0 = none (repeating rounds then replay captured graphs)")
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1], help="opts.graphs (used when --profile 0)")
-    ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus"], help="instance of --workload ops")
+    ap.add_argument("--ops-instance", default="mc", choices=["mc", "torus", "lowrank"], help="instance of --workload ops")
     ap.add_argument("--autotune", type=int, default=0, help="1: tune the tile schedule at create (timed outside the steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--cpu-c0-solve", action="store_true",

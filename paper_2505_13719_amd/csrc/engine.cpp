@@ -167,7 +167,7 @@ struct Layout {
   size_t eptr, econ, ea64, ew64, cptr, cent, epair, Bpair;
   size_t buf[NBUF], m_xt, m_yp, p, yp, TY, Ty, m64, m64_low, V, V2, w, lzv, hcoef, Z0, part, red_stage, red_count, gram, tiles,
       ilist;
-  size_t Kc, Kc64, Dc, lc_con, lc_off, lc_doff, lc_of_con, lc_part, lc_Y, lc_Z, lc_T, lc_v, lc_zv, lc_Tv;
+  size_t Kc, Kc64, Dc, lc_con, lc_off, lc_doff, lc_of_con, lc_term, lc_part, lc_Y, lc_Z, lc_T, lc_v, lc_zv, lc_Tv, lc_W[2], lc_wv;
   size_t cdp_d, cdp_S, cdp_S2, cdp_T, cdp_Tv, cdp_wv, cdp_W[2];
   size_t total;
 };
@@ -239,6 +239,7 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
     L.lc_off = c.take((nlc + 1) * 4);
     L.lc_doff = c.take(nlc * 4);
     L.lc_of_con = c.take(m * 4);
+    L.lc_term = c.take(rk * 4);
     L.lc_part = c.take(nt * rk * R_MAX * 8);
     L.lc_Y = c.take(rk * R_MAX * 8);
     L.lc_Z = c.take(2 * rk * R_MAX * 8);
@@ -246,6 +247,8 @@ static Layout make_layout(const HostProblem &hp, int prec, int Rcap, int kmax) {
     L.lc_v = c.take(rk * 8);
     L.lc_zv = c.take(rk * 8);
     L.lc_Tv = c.take(nlc * 8);
+    for (int z = 0; z < 2; ++z) L.lc_W[z] = c.take(n * Rcap * 8);
+    L.lc_wv = c.take(n * 8);
   }
   if (hp.cdp_L > 0) {
     // masks, spectra for up to Rcap columns (and their scaled copy), the
@@ -583,8 +586,11 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     put(base, L.lc_off, h.lc_off, st);
     put(base, L.lc_doff, h.lc_doff, st);
     put(base, L.lc_of_con, h.lc_of_con, st);
+    put(base, L.lc_term, h.lc_term, st);
     (void)hipMemsetAsync(base + L.lc_Z, 0, 2 * (size_t)h.rk * R_MAX * 8, st);
     (void)hipMemsetAsync(base + L.lc_zv, 0, (size_t)h.rk * 8, st);
+    for (int z = 0; z < 2; ++z) (void)hipMemsetAsync(base + L.lc_W[z], 0, (size_t)h.n * S.Rcap * 8, st);
+    (void)hipMemsetAsync(base + L.lc_wv, 0, (size_t)h.n * 8, st);
   }
   if (h.cdp_L > 0) {
     put(base, L.cdp_d, h.cdp_d, st);
@@ -681,6 +687,7 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     D.lc_off = (const int32_t *)at(L.lc_off);
     D.lc_doff = (const int32_t *)at(L.lc_doff);
     D.lc_of_con = (const int32_t *)at(L.lc_of_con);
+    D.lc_term = (const int32_t *)at(L.lc_term);
     D.lc_part = (double *)at(L.lc_part);
     D.lc_Y = (double *)at(L.lc_Y);
     D.lc_Z = (double *)at(L.lc_Z);
@@ -688,6 +695,8 @@ hallar_status slot_load(Pool &P, int s, HostProblem &&hp, std::string &err) {
     D.lc_v = (double *)at(L.lc_v);
     D.lc_zv = (double *)at(L.lc_zv);
     D.lc_Tv = (double *)at(L.lc_Tv);
+    for (int z = 0; z < 2; ++z) D.lc_W[z] = (double *)at(L.lc_W[z]);
+    D.lc_wv = (double *)at(L.lc_wv);
   }
   D.cdp_L = h.cdp_L;
   D.cdp_nc = h.cdp_nc;
@@ -920,12 +929,17 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       if (gni > 0) {
         if (max_rk > 0) {
           // the constraints' low-rank parts of T (Algorithm 3) before the AL
-          // epilogue of each constraint, their SpMM coefficients after it
+          // epilogue of each constraint; their SpMM block after it, when the
+          // pair values are formed for an SpMM (Algorithm 5)
           op_lc_kty(prec, R, st, T, nt, D, max_rk, xrole, 0);
+          op_lc_sum(st, GL, gni, D, max_rk, R, 0);
           op_lc_red(st, GL, gni, D, LC_Y_T, R, zsel);
         }
         op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
-        if (max_rk > 0) op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
+        if (max_rk > 0 && msel >= 0) {
+          op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
+          op_lc_kz(prec, R, st, T, nt, D, zsel, 0);
+        }
         if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
       }
     } else {
@@ -938,6 +952,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         op_sddmm(prec, R, st, T, nt, D, xrole, msel, wT, wyp);
         if (max_rk > 0) {
           op_lc_kty(prec, R, st, T, nt, D, max_rk, xrole, 0);
+          op_lc_sum(st, GL, gni, D, max_rk, R, 0);
           op_lc_red(st, GL, gni, D, LC_Y_T, R, zsel);
         }
       }
@@ -950,7 +965,10 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
       {
         ProfScope po(P, KC_OTHER, 0.0, st);
         op_gen_constraints(prec, st, GL, gni, g.maxm, D, wT);
-        if (max_rk > 0) op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
+        if (max_rk > 0 && msel >= 0) {
+          op_lc_red(st, GL, gni, D, LC_Z, R, zsel);
+          op_lc_kz(prec, R, st, T, nt, D, zsel, 0);
+        }
         if (msel >= 0) op_pairvals(prec, st, GL, gni, g.maxp, D, msel, nullptr, 1);
       }
       if (msel >= 0)
@@ -1057,7 +1075,9 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         if (max_rk > 0) {
           // K^T v_j and its coefficients for the SpMV's low-rank parts
           op_lc_kty(prec, R, st, T, nt, D, max_rk, 0, 1);
+          op_lc_sum(st, IL, ni, D, max_rk, 1, 1);
           op_lc_red(st, IL, ni, D, LC_V_LZ, 1, 0);
+          op_lc_kz(prec, 1, st, T, nt, D, 0, 1);
         }
         for (int q : cdps) {
           // the coded-diffraction part of G v_j
@@ -1104,6 +1124,7 @@ static void launch_group(Pool &P, const Group &g, hipStream_t st) {
         op_fw_den(st, T, nt, D);
         if (gni > 0 && max_rk > 0) {
           op_lc_kty(prec, R, st, T, nt, D, max_rk, 0, 2);
+          op_lc_sum(st, GL, gni, D, max_rk, 1, 2);
           op_lc_red(st, GL, gni, D, LC_V_FW, 1, 0);
         }
         if (gni > 0) op_fw_den_gen(st, GL, gni, g.maxm, D);
@@ -2181,6 +2202,7 @@ hallar_status op_eval_AUUt(Pool &P, int s, const void *U, int r, int64_t ldu, do
   op_sddmm(P.prec, R, st, T_, nt, D, RU, -1, 1, 0, S.hp.direct && S.hp.m > 0 ? T + 1 : nullptr);
   if (S.hp.rk > 0) {
     op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
+    op_lc_sum(st, IL, 1, D, S.hp.rk, R, 0);
     op_lc_red(st, IL, 1, D, LC_Y_T, R, 0);
   }
   if (S.hp.cdp_L > 0) {
@@ -2319,7 +2341,9 @@ hallar_status op_adjoint(Pool &P, int s, const double *p, const void *U, int r, 
   if (S.hp.rk > 0) {
     // blockdiag(p_l D_l) K^T U for the constraints' low-rank parts (Algorithm 5)
     op_lc_kty(P.prec, R, st, T_, nt, D, S.hp.rk, RU, 0);
+    op_lc_sum(st, IL, 1, D, S.hp.rk, R, 0);
     op_lc_red(st, IL, 1, D, LC_Y_Z, R, 0, p);
+    op_lc_kz(P.prec, R, st, T_, nt, D, 0, 0);
   }
   if (S.hp.cdp_L > 0) {
     // the coded-diffraction block D_l^H F^H (p_l * F D_l U)

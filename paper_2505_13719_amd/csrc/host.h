@@ -47,6 +47,7 @@ struct HostProblem {
   int32_t rk = 0, nlc = 0;
   std::vector<double> Kc, Dc;
   std::vector<int32_t> lc_con, lc_off, lc_doff, lc_of_con;
+  std::vector<int32_t> lc_term;  // term of each column of K (rk)
   // coded-diffraction constraints (Section 5.4) on the real form: L masks of
   // n_c = n / 2 complex entries, interleaved (re, im), pattern-major
   int32_t cdp_L = 0, cdp_nc = 0;

@@ -161,14 +161,16 @@ struct InstDev {
   int32_t rk, nlc;
   const void *Kc;
   const double *Kc64, *Dc;
-  const int32_t *lc_con, *lc_off, *lc_doff, *lc_of_con;
+  const int32_t *lc_con, *lc_off, *lc_doff, *lc_of_con, *lc_term;  // lc_term: term of each column k
   double *lc_part;   // per tile: rk x R_MAX partial sums of K^T X (or K^T v)
   double *lc_Y;      // K^T X, rk x R_MAX
-  double *lc_Z;      // 2 slots (zsel) of blockdiag(y'_l D_q) K^T X, rk x R_MAX each
+  double *lc_Z;      // 2 slots (zsel) of blockdiag(y'_l D_q) K^T X: rk x R (rows of stride R) in rk x R_MAX each
   double *lc_T;      // nlc: Tr(D_q (K_q^T X)(K_q^T X)^T), the low-rank part of A_l . X X^T
   double *lc_v;      // rk: K^T v for a vector v
   double *lc_zv;     // rk: blockdiag(y''_l D_q) K^T v (added by the Lanczos SpMV)
   double *lc_Tv;     // nlc: (K_q^T v)^T D_q (K_q^T v) (Frank-Wolfe step size)
+  double *lc_W[2];   // per Z-slot: the adjoint's low-rank block K Z, n x R (rows of stride R)
+  double *lc_wv;     // n: K lc_zv (the Lanczos product's low-rank part)
   // coded-diffraction constraints (Section 5.4) on the real form, n = 2 nc:
   // L masks d (nc complex each); spectra S of d_l * u_c, transform
   // (l R + c) contiguous (the FFTs' batch order), and their scaled copy S2;
@@ -182,9 +184,10 @@ struct InstDev {
   double *cdp_W[2];
 };
 
-// Reductions of the constraints' low-rank parts (k_lc_red): Y = K^T X and
-// lc_T; lc_Z from the Y in place with the multipliers (I.yp or given); Y
-// then lc_Z; K^T v then lc_zv (Lanczos, multipliers I.yp); K^T v then lc_Tv.
+// Products of the constraints' low-rank parts (k_lc_red, after k_lc_sum has
+// formed Y = K^T X or K^T v): lc_T from Y; lc_Z from Y with the multipliers
+// (I.yp or given); both; lc_zv from K^T v (Lanczos, multipliers I.yp);
+// lc_Tv from K^T v.
 enum LcMode : int { LC_Y_T = 0, LC_Z, LC_Y_Z, LC_V_LZ, LC_V_FW };
 
 // Scratch of the allocation-free evaluation: one static device array per GPU.

@@ -640,15 +640,10 @@ __device__ __forceinline__ void spmm_epi_apply(const InstDev &I, const InstParam
     for (int e = 0; e < NC; ++e) w[e] += kv * Z0[t * R_MAX + ch * NC + e];
   }
   if (I.rk > 0) {
-    // constraints' low-rank parts: + K_i . (blockdiag(y_l D_l) K^T X) (Algorithm 5)
-    const int rk = I.rk;
-    const T *__restrict__ Kc = reinterpret_cast<const T *>(I.Kc) + (size_t)i * rk;
-    const double *__restrict__ Zc = I.lc_Z + (size_t)a.zsel * rk * R_MAX + ch * NC;
-    for (int k = 0; k < rk; ++k) {
-      const double kv = (double)Kc[k];
+    // constraints' low-rank parts: K_i . (blockdiag(y_l D_l) K^T X) (Algorithm 5), formed by k_lc_kz
+    const double *__restrict__ Wc = I.lc_W[a.zsel] + (size_t)i * R + ch * NC;
 #pragma unroll
-      for (int e = 0; e < NC; ++e) w[e] += kv * Zc[(size_t)k * R_MAX + e];
-    }
+    for (int e = 0; e < NC; ++e) w[e] += Wc[e];
   }
   if (I.cdp_L > 0) {
     // coded-diffraction constraints: their adjoint block, formed by the FFTs
@@ -1546,10 +1541,7 @@ __global__ __launch_bounds__(BLOCK) void k_lz_spmv_dots(const Tile *__restrict__
     for (int o = TS / 2; o >= 1; o >>= 1) w += shfl_xor(w, o);
     if (strm == 0) {
       for (int t = 0; t < I.r0; ++t) w += I.K064[(size_t)i * I.r0 + t] * kd[t];
-      if (I.rk > 0) {
-        const double *Kc = I.Kc64 + (size_t)i * I.rk;
-        for (int k = 0; k < I.rk; ++k) w += Kc[k] * I.lc_zv[k];
-      }
+      if (I.rk > 0) w += I.lc_wv[i];  // constraints' low-rank parts of G v (k_lc_kz)
       if (I.cdp_L > 0) w += I.cdp_wv[i];  // coded-diffraction part of G v
       // shifted three-term form: the Gram-Schmidt dots then see only the
       // small remainder, so the DGKS test can skip the second pass (the
@@ -2316,6 +2308,43 @@ void op_reduce(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, in
 // Per tile and group of 64 columns of K: partial K^T X (vsrc 0: the factor
 // of role xrole, R columns) or K^T v (vsrc 1: the Lanczos vector being
 // multiplied; 2: the Ritz vector lzv), into lc_part[tile][k][c].
+// Per tile and group of 64 columns of K: partial K^T X (vsrc 0: the factor
+// of role xrole, R columns, K in the operator type) or K^T v (vsrc 1: the
+// Lanczos vector being multiplied; 2: the Ritz vector lzv; R = 1, K in
+// FP64), into lc_part[tile][k][c] (rows of stride R).  Lane = column k of
+// K (coalesced reads of each row of K); the four waves take every fourth
+// row of the tile and their sums are added in wave order through LDS.
+template <typename T, int RC>
+__device__ __forceinline__ void lc_kty_tile(const Tile &tl, const InstDev &I, const T *__restrict__ K,
+                                            const T *__restrict__ X, const double *__restrict__ v, int rk, int k,
+                                            double *out) {
+  __shared__ double s_red[BLOCK / 64][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[RC];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+  if (k < rk)
+    for (int i = tl.row0 + wave; i < tl.row1; i += BLOCK / 64) {
+      const double kv = (double)K[(size_t)i * rk + k];
+      if (X) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] += kv * (double)X[(size_t)i * RC + c];
+      } else {
+        acc[0] += kv * v[i];
+      }
+    }
+  for (int c = 0; c < RC; ++c) {
+    s_red[wave][lane] = acc[c];
+    __syncthreads();
+    if (wave == 0 && k < rk) {
+      double t = s_red[0][lane];
+      for (int w = 1; w < BLOCK / 64; ++w) t += s_red[w][lane];
+      out[(size_t)k * RC + c] = t;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(BLOCK) void k_lc_kty(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                   int32_t xrole, int32_t vsrc) {
@@ -2327,47 +2356,15 @@ __global__ __launch_bounds__(BLOCK) void k_lc_kty(const Tile *__restrict__ tiles
   if (rk == 0 || (int)blockIdx.y * 64 >= rk) return;  // uniform per block
   const InstParams &P = *I.prm;
   if (vsrc == 1 && P.lz_steps <= 0) return;
-  const int k = blockIdx.y * 64 + (threadIdx.x & 63), cq = threadIdx.x >> 6;
-  if (k >= rk) return;
-  double *out = I.lc_part + ((size_t)tl.lt * rk + k) * R_MAX;
+  const int k = blockIdx.y * 64 + (threadIdx.x & 63);
   if (vsrc == 0) {
-    const T *__restrict__ X = role_ptr<T>(I, P, xrole);
-    const T *__restrict__ K = reinterpret_cast<const T *>(I.Kc);
-    constexpr int PER = (R + 3) / 4;
-    double acc[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) acc[u] = 0.0;
-    for (int i = tl.row0; i < tl.row1; ++i) {
-      const double kv = (double)K[(size_t)i * rk + k];
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int c = cq + 4 * u;
-        if (c < R) acc[u] += kv * (double)X[(size_t)i * R + c];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int c = cq + 4 * u;
-      if (c < R) out[c] = acc[u];
-    }
+    double *out = I.lc_part + (size_t)tl.lt * rk * R;
+    lc_kty_tile<T, R>(tl, I, reinterpret_cast<const T *>(I.Kc), role_ptr<T>(I, P, xrole), nullptr, rk, k, out);
   } else {
-    if (cq != 0) return;
+    double *out = I.lc_part + (size_t)tl.lt * rk;
     const double *v = vsrc == 1 ? lz_basis(I, P) + (size_t)P.lz_j * I.n : I.lzv;
-    double acc = 0.0;
-    for (int i = tl.row0; i < tl.row1; ++i) acc += I.Kc64[(size_t)i * rk + k] * v[i];
-    out[0] = acc;
+    lc_kty_tile<double, 1>(tl, I, I.Kc64, nullptr, v, rk, k, out);
   }
-}
-
-// term of column k: lc_off[q] <= k < lc_off[q + 1]
-__device__ __forceinline__ int lc_term_of(const InstDev &I, int k) {
-  int lo = 0, hi = I.nlc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (I.lc_off[mid] <= k) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
 }
 
 // sum_ab D_q[a][b] <Y_a, Y_b> over c < R for term q (Y rows of stride ld)
@@ -2401,17 +2398,8 @@ __global__ __launch_bounds__(RBLOCK) void k_lc_red(const int32_t *__restrict__ i
   const InstParams &P = *I.prm;
   if (a.mode == LC_V_LZ && P.lz_steps <= 0) return;
   const bool vec = a.mode == LC_V_LZ || a.mode == LC_V_FW;
-  const int R = vec ? 1 : a.R, ld = vec ? 1 : R_MAX, nt = I.ntiles;
-  double *Y = vec ? I.lc_v : I.lc_Y;
-  if (a.mode != LC_Z) {
-    for (int q = threadIdx.x; q < rk * R; q += blockDim.x) {
-      const int k = q / R, c = q - (q / R) * R;
-      double s = 0.0;
-      for (int t = 0; t < nt; ++t) s += I.lc_part[((size_t)t * rk + k) * R_MAX + c];
-      Y[(size_t)k * ld + c] = s;
-    }
-    __syncthreads();
-  }
+  const int R = vec ? 1 : a.R, ld = vec ? 1 : R_MAX;
+  const double *Y = vec ? I.lc_v : I.lc_Y;  // summed over the tiles by k_lc_sum
   if (a.mode == LC_Y_T || a.mode == LC_V_FW) {
     double *out = a.mode == LC_Y_T ? I.lc_T : I.lc_Tv;
     // small terms: one thread each; larger ones: the whole block, in turn
@@ -2432,17 +2420,93 @@ __global__ __launch_bounds__(RBLOCK) void k_lc_red(const int32_t *__restrict__ i
     }
     return;
   }
-  // coefficients blockdiag(y_l D_q) Y: lc_Z slot zsel (rk x R_MAX) or lc_zv (vector)
+  // coefficients blockdiag(y_l D_q) Y: lc_Z slot zsel (rk x R, rows of
+  // stride R) or lc_zv (vector)
   const double *y = a.mult ? a.mult : I.yp;
   double *Z = vec ? I.lc_zv : I.lc_Z + (size_t)a.zsel * rk * R_MAX;
   for (int q2 = threadIdx.x; q2 < rk * R; q2 += blockDim.x) {
     const int k = q2 / R, c = q2 - (q2 / R) * R;
-    const int q = lc_term_of(I, k);
+    const int q = I.lc_term[k];
     const int o = I.lc_off[q], rl = I.lc_off[q + 1] - o, ai = k - o;
     const double *Dq = I.Dc + I.lc_doff[q];
     double s = 0.0;
     for (int b = 0; b < rl; ++b) s += Dq[(size_t)ai * rl + b] * Y[(size_t)(o + b) * ld + c];
-    Z[(size_t)k * ld + c] = y[I.lc_con[q] - 1] * s;
+    Z[(size_t)k * R + c] = y[I.lc_con[q] - 1] * s;
+  }
+}
+
+// K^T X (or K^T v) summed over the tiles: a wave per 8 consecutive (k, c)
+// entries, its lanes in 8 groups taking every eighth tile (each load reads
+// 8 consecutive entries of one tile), then the groups added by a butterfly
+// in fixed order.  Many workgroups per instance.
+constexpr int LC_QW = 8;
+__global__ __launch_bounds__(BLOCK) void k_lc_sum(const int32_t *__restrict__ ilist,
+                                                  const InstDev *__restrict__ insts, int32_t R, int32_t vec) {
+  const InstDev &I = insts[ilist[blockIdx.x]];
+  const int rk = I.rk;
+  if (rk == 0) return;
+  const InstParams &P = *I.prm;
+  if (vec == 1 && P.lz_steps <= 0) return;
+  const int Rn = vec ? 1 : R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qq = lane % LC_QW, tq = lane / LC_QW;
+  const int q = (blockIdx.y * (BLOCK / 64) + wave) * LC_QW + qq;
+  const int total = rk * Rn;
+  if ((blockIdx.y * (BLOCK / 64) + wave) * LC_QW >= total) return;  // whole wave
+  const int nt = I.ntiles;
+  const size_t stride = (size_t)total;
+  double s = 0.0;
+  if (q < total)
+    for (int t = tq; t < nt; t += 64 / LC_QW) s += I.lc_part[(size_t)t * stride + q];
+  for (int o = LC_QW; o < 64; o <<= 1) s += shfl_xor(s, o);
+  if (tq == 0 && q < total) {
+    const int k = q / Rn, c = q - k * Rn;
+    if (vec) I.lc_v[k] = s;
+    else I.lc_Y[(size_t)k * R_MAX + c] = s;
+  }
+}
+
+// The constraints' low-rank block of the adjoint, K (blockdiag(y_l D_l) K^T X)
+// (Algorithm 5), for the rows of each tile: a wave per row, its lanes over
+// the columns k of K (coalesced reads of the row of K), a wave reduction per
+// output column.  vec 0: R columns from the Z-slot zsel into lc_W[zsel]
+// (rows of stride R), K in the operator type; vec 1: the Lanczos vector's
+// coefficients lc_zv into lc_wv, K in FP64.
+template <typename T, int R>
+__global__ __launch_bounds__(BLOCK) void k_lc_kz(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                 int32_t zsel, int32_t vec) {
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const int rk = I.rk;
+  if (rk == 0) return;
+  const InstParams &P = *I.prm;
+  if (vec && P.lz_steps <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = tl.row0 + wave; i < tl.row1; i += BLOCK / 64) {
+    double acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+    if (vec) {
+      const double *__restrict__ Krow = I.Kc64 + (size_t)i * rk;
+      for (int k = lane; k < rk; k += 64) acc[0] += Krow[k] * I.lc_zv[k];
+    } else {
+      const T *__restrict__ Krow = reinterpret_cast<const T *>(I.Kc) + (size_t)i * rk;
+      const double *__restrict__ Z = I.lc_Z + (size_t)zsel * rk * R_MAX;
+#pragma unroll 4
+      for (int k = lane; k < rk; k += 64) {
+        const double kv = (double)Krow[k];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] += kv * Z[(size_t)k * R + c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0) {
+      if (vec) I.lc_wv[i] = acc[0];
+      else
+#pragma unroll
+        for (int c = 0; c < R; ++c) I.lc_W[zsel][(size_t)i * R + c] = acc[c];
+    }
   }
 }
 
@@ -2462,6 +2526,34 @@ void op_lc_kty(int prec, int R, hipStream_t s, const Tile *t, int nt, const Inst
   if (vsrc != 0) R = is64(prec) ? 2 : 4;  // the vector forms read FP64 K and v: any instantiation
   if (is64(prec)) HL_DISPATCH_G(double, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
   else HL_DISPATCH_G(float, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
+}
+void op_lc_sum(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int max_rk, int R, int vec) {
+  if (ni <= 0 || max_rk <= 0) return;
+  const int Rn = vec ? 1 : R;
+  const int per_block = (BLOCK / 64) * LC_QW;
+  hipLaunchKernelGGL(k_lc_sum, dim3(ni, (max_rk * Rn + per_block - 1) / per_block), dim3(BLOCK), 0, s, ilist, d, R,
+                     vec);
+}
+template <typename T, int R>
+static void l_lc_kz(hipStream_t s, const Tile *t, int nt, const InstDev *d, int zsel, int vec) {
+  hipLaunchKernelGGL((k_lc_kz<T, R>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel, vec);
+}
+void op_lc_kz(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int zsel, int vec) {
+  if (nt <= 0) return;
+  if (vec) {
+    l_lc_kz<double, 1>(s, t, nt, d, 0, 1);
+    return;
+  }
+  switch (R) {
+#define HL_KZ(RR)                                                  \
+  case RR:                                                         \
+    if (is64(prec)) l_lc_kz<double, RR>(s, t, nt, d, zsel, 0);     \
+    else l_lc_kz<float, RR>(s, t, nt, d, zsel, 0);                 \
+    break;
+    HL_KZ(2) HL_KZ(4) HL_KZ(8) HL_KZ(16) HL_KZ(32) HL_KZ(64)
+#undef HL_KZ
+    default: break;
+  }
 }
 void op_lc_red(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int mode, int R, int zsel,
                const double *mult) {

@@ -25,6 +25,8 @@ void op_put_params(hipStream_t s, InstParams *dst, const InstParams &v);
 // R columns; 1: the Lanczos vector being multiplied; 2: the Ritz vector),
 // then per instance the mode's reduction (LcMode).
 void op_lc_kty(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int max_rk, int xrole, int vsrc);
+void op_lc_sum(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int max_rk, int R, int vec);
+void op_lc_kz(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int zsel, int vec);
 void op_lc_red(hipStream_t s, const int32_t *ilist, int ni, const InstDev *d, int mode, int R, int zsel,
                const double *mult = nullptr);
 void op_sddmm(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int xrole, int msel, int wT, int wyp,

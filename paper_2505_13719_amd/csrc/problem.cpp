@@ -320,6 +320,7 @@ std::string build_host_problem(const hallar_problem *p, HostProblem &hp, hallar_
         doff += (int64_t)rl * rl;
         col += rl;
         hp.lc_off.push_back(col);
+        hp.lc_term.insert(hp.lc_term.end(), (size_t)rl, (int32_t)hp.lc_con.size() - 1);
       }
       hp.nlc = (int32_t)hp.lc_con.size();
     }
