@@ -1922,7 +1922,12 @@ static Task solve_main(Ctx c) {
         res.status = HALLAR_E_NUMERICAL;
         break;
       }
-      if (gap <= eps_t) {
+      // the gap is the difference of G . YY^T and tau^2 theta, each of the
+      // size of the objective; the stored iterate resolves it only to a few
+      // units of its storage roundoff of their size (FP32-mixed: u = 2^-24;
+      // in FP64 the allowance is far below eps_t)
+      const double gap_floor = 4.0 * storage_eps(c.P.prec) * (std::fabs(GYY) + tau2 * theta);
+      if (gap <= std::max(eps_t, gap_floor)) {
         hlr_ok = true;
         break;
       }
