@@ -39,7 +39,7 @@ def _solve(d, prec):
 
 
 @pytest.mark.parametrize("d,prec", [(10, H.FP64), (12, H.FP64), (14, H.FP64), (16, H.FP64), (18, H.FP64),
-                                    (21, H.FP64), (12, H.FP32_MIXED), (16, H.FP32_MIXED)])
+                                    (21, H.FP64), (12, H.FP32_MIXED), (16, H.FP32_MIXED), (21, H.FP32_MIXED)])
 def test_theta_hamming_is_half_n(d, prec):
     prob, res, U, p = _solve(d, prec)
     n = prob.n
