@@ -8,8 +8,9 @@
  *
  * with the factorisation X = U U^T.  Each data matrix A_l (A_0 = C) is given
  * in the hybrid sparse / low-rank form of Section 3.2 (eq. HSLR-rep-body):
- * a sparse symmetric part listed by its upper-triangle entries plus, for the
- * objective only, a low-rank term K D K^T.
+ * a sparse symmetric part listed by its upper-triangle entries plus low-rank
+ * terms K D K^T; or, for complex phase retrieval (Section 5.4), the
+ * coded-diffraction constraints applied on the fly with FFTs.
  *
  * Conventions shared by every call
  *   - Every call returns hallar_status; nothing throws or aborts across the
@@ -25,7 +26,10 @@
  *   - Dense row-major layouts: element (i, c) of an n x r matrix with
  *     leading dimension ld is at [i * ld + c].
  *   - All allocation happens in hallar_create / hallar_pool_*; the operator
- *     and solve calls allocate nothing.
+ *     and solve calls allocate nothing, except that a coded-diffraction
+ *     instance makes the FFT plan for a column count it has not met before
+ *     on first use (rocFFT may allocate then; its work buffer grows if that
+ *     plan needs more) and hallar_get_solution stages its tile list.
  */
 #ifndef HALLAR_H
 #define HALLAR_H
