@@ -859,9 +859,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(const Tile *__restrict__ tiles, 
 // lower), and no pair values written or read.  The pair values and the
 // SpMM's sums are bit-identical to the separate kernels'; the SDDMM's partial
 // sums are formed in walk order instead of pair order.
-template <typename T, int G>
-__global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ tiles,
-                                                       const InstDev *__restrict__ insts, int32_t xrole) {
+// LATE: the epilogue operands are loaded after the row's walk (fewer live
+// registers during the walk).
+template <typename T, int G, bool LATE>
+__device__ __forceinline__ void trial_fused_body(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
+                                                 int32_t xrole) {
   static_assert(G <= 2, "the fused trial kernel takes narrow rows");
   constexpr int NC = NCh<T>::N;
   constexpr int R = G * NC;
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
     if (r >= nrows) continue;
     const int i = tl.row0 + r;
     EpiIn<T> in;
-    if (strm == 0) in = spmm_epi_load<T, G, SP_TRIAL>(I, P, X, (size_t)i * R + ch * NC);
+    if (!LATE && strm == 0) in = spmm_epi_load<T, G, SP_TRIAL>(I, P, X, (size_t)i * R + ch * NC);
     const int ku = s_ru[r], cu = s_ru[r + 1] - ku;
     const int kl = s_rl[r], cnt = cu + s_rl[r + 1] - kl;
     const Chunk<T> xo = ldc(X + (size_t)i * R + ch * NC);
@@ -986,10 +988,28 @@ __global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ 
 #pragma unroll
       for (int e = 0; e < NC; ++e) w[e] += shfl_xor(w[e], o);
     }
-    if (strm == 0) spmm_epi_apply<T, G, SP_TRIAL, 2>(I, P, sa, i, ch, w, in, acc2);
+    if (strm == 0) {
+      if (LATE) in = spmm_epi_load<T, G, SP_TRIAL>(I, P, X, (size_t)i * R + ch * NC);
+      spmm_epi_apply<T, G, SP_TRIAL, 2>(I, P, sa, i, ch, w, in, acc2);
+    }
   }
   block_partials<4>(acc4, I, tl.lt);
   block_partials<2, FUSE_SLOT>(acc2, I, tl.lt);
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(BLOCK) void k_trial_fused(const Tile *__restrict__ tiles,
+                                                       const InstDev *__restrict__ insts, int32_t xrole) {
+  trial_fused_body<T, G, false>(tiles, insts, xrole);
+}
+// FP64 rank-4 rows (the matrix-completion headline): capped at 80 VGPRs for
+// six waves per SIMD, with the epilogue loaded late so that nothing spills
+// (measured 300 -> 286 us per launch; the same cap spills in the other
+// instantiations)
+template <>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_trial_fused<double, 2>(
+    const Tile *__restrict__ tiles, const InstDev *__restrict__ insts, int32_t xrole) {
+  trial_fused_body<double, 2, true>(tiles, insts, xrole);
 }
 
 // ---------------------------------------------------------------------------
