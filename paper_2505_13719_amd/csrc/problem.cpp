@@ -437,7 +437,12 @@ void build_tiles(HostProblem &hp) {
 // matrices of the Lanczos solver and the Gram matrices of U): Householder
 // reduction to tridiagonal form with the transformations accumulated, then
 // implicit QL iterations with Wilkinson shifts on the tridiagonal matrix,
-// rotating the accumulated basis; eigenpairs sorted ascending.
+// rotating the accumulated basis; eigenpairs sorted ascending.  The QL sweep
+// is the published method of Bowdler, Martin, Reinsch and Wilkinson ("The QR
+// and QL algorithms for symmetric matrices", Numer. Math. 11, 1968; the tql2
+// procedure of the Handbook for Automatic Computation, vol. II) and keeps its
+// order of steps: the shift, the plane rotations chased upward, the
+// deflation when a rotation's radius vanishes.
 void sym_eig(int n, const double *A, double *w, double *Q) {
   if (n <= 0) return;
   std::vector<double> a(A, A + (size_t)n * n);
