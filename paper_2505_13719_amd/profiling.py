@@ -3,6 +3,7 @@
     python -m paper_2505_13719_amd.profiling trace <kernel_trace.csv>
     python -m paper_2505_13719_amd.profiling counters <fetch counter_collection.csv> <write counter_collection.csv>
         [--copy-kib KIB]
+    python -m paper_2505_13719_amd.profiling l2 <counter_collection.csv>
 
 `trace` prints, per kernel name, the dispatch count, average and total
 duration and share of the traced kernel time (from rocprofv3
@@ -12,6 +13,9 @@ per launch after scaling each counter by what it reads for a plain device
 copy of known size (the largest torch copy kernel in the same run moves
 --copy-kib KiB each way, 1 GiB by default), plus one machine-readable line
 per kernel: traffic_bytes_per_launch[<kernel>] = <bytes> dispatches=<n>.
+`l2` prints, per kernel, the L2 (TCC) hits and misses per dispatch, the hit
+rate and the read requests the L2 sends to memory (one --pmc pass with
+TCC_HIT_sum, TCC_MISS_sum, TCC_EA0_RDREQ_sum and TCC_EA0_RDREQ_32B_sum).
 """
 import csv
 import sys
@@ -90,9 +94,26 @@ def counters(fetch_path, write_path, copy_kib=1 << 20):
     print("\n".join(lines))
 
 
+def l2(path, top=12):
+    c = {k: _counter(path, k) for k in ("TCC_HIT_sum", "TCC_MISS_sum", "TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum")}
+    names = sorted(c["TCC_MISS_sum"], key=lambda k: -c["TCC_MISS_sum"][k][0] * c["TCC_MISS_sum"][k][1])
+    print("| kernel | dispatches | L2 hits / launch | L2 misses / launch | hit rate | memory read requests / launch "
+          "| of them 32 B |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for name in names[:top]:
+        h, n = c["TCC_HIT_sum"].get(name, (0.0, 0))
+        m = c["TCC_MISS_sum"][name][0]
+        rq = c["TCC_EA0_RDREQ_sum"].get(name, (0.0, 0))[0]
+        r32 = c["TCC_EA0_RDREQ_32B_sum"].get(name, (0.0, 0))[0]
+        rate = h / (h + m) if h + m > 0 else 0.0
+        print(f"| `{name}` | {n} | {h:.4g} | {m:.4g} | {rate:.3f} | {rq:.4g} | {r32:.4g} |")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2])
+    elif sys.argv[1] == "l2":
+        l2(sys.argv[2])
     else:
         kib = 1 << 20
         if "--copy-kib" in sys.argv:
