@@ -4,6 +4,7 @@
     python -m paper_2505_13719_amd.profiling counters <fetch counter_collection.csv> <write counter_collection.csv>
         [--copy-kib KIB]
     python -m paper_2505_13719_amd.profiling l2 <counter_collection.csv>
+    python -m paper_2505_13719_amd.profiling pmc <counter_collection.csv> [--match TEXT]
 
 `trace` prints, per kernel name, the dispatch count, average and total
 duration and share of the traced kernel time (from rocprofv3
@@ -16,6 +17,15 @@ per kernel: traffic_bytes_per_launch[<kernel>] = <bytes> dispatches=<n>.
 `l2` prints, per kernel, the L2 (TCC) hits and misses per dispatch, the hit
 rate and the read requests the L2 sends to memory (one --pmc pass with
 TCC_HIT_sum, TCC_MISS_sum, TCC_EA0_RDREQ_sum and TCC_EA0_RDREQ_32B_sum).
+`pmc` prints, for the kernels whose names contain TEXT (default: this
+library's), every counter of the pass averaged per dispatch, and where the
+pass holds them (GRBM_GUI_ACTIVE is summed over the 8 XCDs, so a dispatch's
+clock count is GRBM_GUI_ACTIVE / 8; 256 CUs, one TA and one TCP each): the
+TCP's mean L2 read latency (TCP_TCC_READ_REQ_LATENCY_sum /
+TCP_TCC_READ_REQ_sum, cycles), the L2 reads in flight per CU on average
+(TCP_TCC_READ_REQ_LATENCY_sum / (256 x cycles), Little's law), the TA's busy
+share (TA_BUSY_avr / cycles) and the share of TCP cycles stalled on L2 data
+(TCP_PENDING_STALL_CYCLES_sum / (256 x cycles)).
 """
 import csv
 import sys
@@ -109,11 +119,53 @@ def l2(path, top=12):
         print(f"| `{name}` | {n} | {h:.4g} | {m:.4g} | {rate:.3f} | {rq:.4g} | {r32:.4g} |")
 
 
+def pmc(path, match="hl::", top=12, cus=256, xcds=8):
+    names = []
+    for r in _rows(path):
+        c = _col(r, "Counter_Name", "CounterName")
+        if c not in names:
+            names.append(c)
+    c = {k: _counter(path, k) for k in names}
+    kern = {k for v in c.values() for k in v if match in k}
+    # heaviest first: by busy cycles over all dispatches when the pass holds
+    # them, else by the counter with the largest total
+    tot = {x: sum(v[0] * v[1] for v in c[x].values()) for x in names}
+    first = "GRBM_GUI_ACTIVE" if "GRBM_GUI_ACTIVE" in c else max(names, key=lambda x: tot[x])
+    order = sorted(kern, key=lambda k: -c[first].get(k, (0.0, 0))[0] * c[first].get(k, (0.0, 0))[1])[:top]
+    derived = []
+    cyc = lambda k: max(c["GRBM_GUI_ACTIVE"][k][0] / xcds, 1.0)  # noqa: E731
+    if "TCP_TCC_READ_REQ_LATENCY_sum" in c and "TCP_TCC_READ_REQ_sum" in c:
+        derived.append(("L2 read latency (cycles)", lambda k: c["TCP_TCC_READ_REQ_LATENCY_sum"][k][0] /
+                        max(c["TCP_TCC_READ_REQ_sum"][k][0], 1.0)))
+        if "GRBM_GUI_ACTIVE" in c:
+            derived.append(("L2 reads in flight per CU",
+                            lambda k: c["TCP_TCC_READ_REQ_LATENCY_sum"][k][0] / (cus * cyc(k))))
+    if "TA_BUSY_avr" in c and "GRBM_GUI_ACTIVE" in c:
+        derived.append(("TA busy", lambda k: c["TA_BUSY_avr"][k][0] / cyc(k)))
+    if "TCP_PENDING_STALL_CYCLES_sum" in c and "GRBM_GUI_ACTIVE" in c:
+        derived.append(("TCP stalled on L2", lambda k: c["TCP_PENDING_STALL_CYCLES_sum"][k][0] / (cus * cyc(k))))
+    names = sorted(names)
+    print("| kernel | dispatches | " + " | ".join(names + [d[0] for d in derived]) + " |")
+    print("|---|---:|" + "---:|" * (len(names) + len(derived)))
+    for k in order:
+        n = c[first].get(k, (0.0, 0))[1]
+        vals = [f"{c[x].get(k, (0.0, 0))[0]:.4g}" for x in names]
+        der = []
+        for _, f in derived:
+            try:
+                der.append(f"{f(k):.3g}")
+            except KeyError:
+                der.append("-")
+        print(f"| `{k}` | {n} | " + " | ".join(vals + der) + " |")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2])
     elif sys.argv[1] == "l2":
         l2(sys.argv[2])
+    elif sys.argv[1] == "pmc":
+        pmc(sys.argv[2], sys.argv[sys.argv.index("--match") + 1] if "--match" in sys.argv else "hl::")
     else:
         kib = 1 << 20
         if "--copy-kib" in sys.argv:
