@@ -2530,6 +2530,99 @@ __global__ __launch_bounds__(BLOCK) void k_lc_kz(const Tile *__restrict__ tiles,
   }
 }
 
+// Wide factors (R >= 16): the same two contractions tiled through LDS, so
+// that a row of X or of Z is read once per block of rows rather than once
+// per row.  K^T X per tile: the block's rows of X staged in LDS, lane =
+// column k of K, wave = a group of R/4 output columns, each (k, c) summed
+// over the tile's rows in row order; into lc_part[tile][k][c] as above.
+template <typename T, int R>
+__global__ __launch_bounds__(BLOCK) void k_lc_kty_wide(const Tile *__restrict__ tiles,
+                                                       const InstDev *__restrict__ insts, int32_t xrole) {
+  static_assert(R >= 16 && R % (BLOCK / 64) == 0, "wide factors only");
+  constexpr int CW = R / (BLOCK / 64);
+  constexpr int RB = 64;
+  __shared__ double sX[RB * R];
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const int rk = I.rk;
+  if (rk == 0 || (int)blockIdx.y * 64 >= rk) return;  // uniform per block
+  const InstParams &P = *I.prm;
+  const T *__restrict__ K = reinterpret_cast<const T *>(I.Kc);
+  const T *__restrict__ X = role_ptr<T>(I, P, xrole);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = blockIdx.y * 64 + lane;
+  double acc[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) acc[j] = 0.0;
+  for (int i0 = tl.row0; i0 < tl.row1; i0 += RB) {
+    const int nr = min(RB, tl.row1 - i0);
+    __syncthreads();  // the previous block's reads of sX are done
+    for (int e = threadIdx.x; e < nr * R; e += BLOCK) sX[e] = (double)X[(size_t)i0 * R + e];
+    __syncthreads();
+    if (k < rk) {
+#pragma unroll 4
+      for (int r = 0; r < nr; ++r) {
+        const double kv = (double)K[(size_t)(i0 + r) * rk + k];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) acc[j] += kv * sX[r * R + wave * CW + j];
+      }
+    }
+  }
+  if (k < rk) {
+    double *out = I.lc_part + (size_t)tl.lt * rk * R + (size_t)k * R + wave * CW;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) out[j] = acc[j];
+  }
+}
+
+// K Z for wide factors: per block of 64 rows of the tile, the columns of K
+// in chunks of 32 -- the chunk of K (transposed, padded) and the matching 32
+// rows of Z staged in LDS -- lane = row, wave = a group of R/4 output
+// columns, each output summed over k in order; into lc_W[zsel].
+template <typename T, int R>
+__global__ __launch_bounds__(BLOCK) void k_lc_kz_wide(const Tile *__restrict__ tiles,
+                                                      const InstDev *__restrict__ insts, int32_t zsel) {
+  static_assert(R >= 16 && R % (BLOCK / 64) == 0, "wide factors only");
+  constexpr int CW = R / (BLOCK / 64);
+  constexpr int RB = 64, KC = 32;
+  __shared__ double sK[KC * (RB + 1)];
+  __shared__ double sZ[KC * R];
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev &I = insts[tl.inst];
+  const int rk = I.rk;
+  if (rk == 0) return;
+  const T *__restrict__ K = reinterpret_cast<const T *>(I.Kc);
+  const double *__restrict__ Z = I.lc_Z + (size_t)zsel * rk * R_MAX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i0 = tl.row0; i0 < tl.row1; i0 += RB) {
+    const int nr = min(RB, tl.row1 - i0);
+    double acc[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) acc[j] = 0.0;
+    for (int k0 = 0; k0 < rk; k0 += KC) {
+      const int kn = min(KC, rk - k0);
+      __syncthreads();  // the previous chunk's reads are done
+      // K[i0 + rr][k0 + kk] -> sK[kk][rr]: consecutive threads read along a row of K
+      for (int e = threadIdx.x; e < RB * KC; e += BLOCK) {
+        const int rr = e / KC, kk = e - rr * KC;
+        sK[kk * (RB + 1) + rr] = (rr < nr && kk < kn) ? (double)K[(size_t)(i0 + rr) * rk + k0 + kk] : 0.0;
+      }
+      for (int e = threadIdx.x; e < kn * R; e += BLOCK) sZ[e] = Z[(size_t)k0 * R + e];
+      __syncthreads();
+      for (int kk = 0; kk < kn; ++kk) {
+        const double kv = sK[kk * (RB + 1) + lane];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) acc[j] += kv * sZ[kk * R + wave * CW + j];
+      }
+    }
+    if (lane < nr) {
+      double *o = I.lc_W[zsel] + (size_t)(i0 + lane) * R + wave * CW;
+#pragma unroll
+      for (int j = 0; j < CW; ++j) o[j] = acc[j];
+    }
+  }
+}
+
 // Parameters of a standalone operator call, passed by value as the kernel's
 // argument (captured when the launch is enqueued, so nothing host-side has to
 // stay unchanged until the stream reaches it).
@@ -2543,6 +2636,18 @@ static void l_lc_kty(hipStream_t s, const Tile *t, int nt, const InstDev *d, int
 void op_lc_kty(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstDev *d, int max_rk, int xrole, int vsrc) {
   if (nt <= 0 || max_rk <= 0) return;
   const int ncg = (max_rk + 63) / 64;
+  if (vsrc == 0 && R >= 16) {
+    switch (R) {
+#define HL_KTYW(RR)                                                                                              \
+  case RR:                                                                                                     \
+    if (is64(prec)) hipLaunchKernelGGL((k_lc_kty_wide<double, RR>), dim3(nt, ncg), dim3(BLOCK), 0, s, t, d, xrole); \
+    else hipLaunchKernelGGL((k_lc_kty_wide<float, RR>), dim3(nt, ncg), dim3(BLOCK), 0, s, t, d, xrole);            \
+    return;
+      HL_KTYW(16) HL_KTYW(32) HL_KTYW(64)
+#undef HL_KTYW
+      default: break;
+    }
+  }
   if (vsrc != 0) R = is64(prec) ? 2 : 4;  // the vector forms read FP64 K and v: any instantiation
   if (is64(prec)) HL_DISPATCH_G(double, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
   else HL_DISPATCH_G(float, R, l_lc_kty, s, t, nt, d, ncg, xrole, vsrc);
@@ -2570,8 +2675,14 @@ void op_lc_kz(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstD
     if (is64(prec)) l_lc_kz<double, RR>(s, t, nt, d, zsel, 0);     \
     else l_lc_kz<float, RR>(s, t, nt, d, zsel, 0);                 \
     break;
-    HL_KZ(2) HL_KZ(4) HL_KZ(8) HL_KZ(16) HL_KZ(32) HL_KZ(64)
+#define HL_KZW(RR)                                                                                            \
+  case RR:                                                                                                  \
+    if (is64(prec)) hipLaunchKernelGGL((k_lc_kz_wide<double, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel); \
+    else hipLaunchKernelGGL((k_lc_kz_wide<float, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel);            \
+    break;
+    HL_KZ(2) HL_KZ(4) HL_KZ(8) HL_KZW(16) HL_KZW(32) HL_KZW(64)
 #undef HL_KZ
+#undef HL_KZW
     default: break;
   }
 }
