@@ -5,8 +5,9 @@ Algorithm 5 for the adjoint).
 * Operators against the FP64 oracle (normwise and entry by entry) on an
   instance mixing sparse-only, low-rank-only and sparse + low-rank
   constraints, terms of rank 1 to 3, two terms on one constraint, and a
-  rank-2 objective term, several tiles, both precisions; the adjoint
-  identity; lambda_min of C + A*(p) against LAPACK on the dense matrix.
+  rank-2 objective term, several tiles, both precisions, factor widths
+  from 3 to 50 (both kernel forms of K^T U and K Z); the adjoint identity;
+  lambda_min of C + A*(p) against LAPACK on the dense matrix.
 * Solves of the real phase retrieval SDP (min tr X s.t. a_l^T X a_l =
   (a_l^T x)^2, every constraint a rank-one term): exact recovery fixes the
   optimum at ||x||^2 (the real analogue of Section 5.4), checked in FP64 and
@@ -33,7 +34,11 @@ UNIT = {H.FP64: U64, H.FP32_MIXED: U32}
 
 
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_MIXED])
-@pytest.mark.parametrize("n,m,r", [(300, 90, 3), (2500, 240, 8), (700, 60, 32)])
+# widths 3 and 8 take the row-per-wave kernels; 12, 20, 32 and 50 (column
+# buckets 16, 32 and 64) the LDS-tiled wide ones, with K columns that end
+# inside a 32-column chunk and tiles longer than one 64-row block (n = 3000)
+@pytest.mark.parametrize("n,m,r", [(300, 90, 3), (2500, 240, 8), (700, 60, 32), (600, 50, 12), (400, 40, 50),
+                                   (3000, 60, 20)])
 def test_lowrank_constraint_operators(prec, n, m, r):
     d = dev()
     dt = torch.float64 if prec == H.FP64 else torch.float32
