@@ -2339,20 +2339,28 @@ __device__ __forceinline__ void lc_kty_tile(const Tile &tl, const InstDev &I, co
                                             const T *__restrict__ X, const double *__restrict__ v, int rk, int k,
                                             double *out) {
   __shared__ double s_red[BLOCK / 64][64];
+  // the rows of X (or v) staged in LDS, 64 rows at a time: every lane reads
+  // the same row, so LDS broadcasts it instead of per-lane vector loads
+  constexpr int RB = 64;
+  __shared__ double s_x[RB * RC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double acc[RC];
 #pragma unroll
   for (int c = 0; c < RC; ++c) acc[c] = 0.0;
-  if (k < rk)
-    for (int i = tl.row0 + wave; i < tl.row1; i += BLOCK / 64) {
-      const double kv = (double)K[(size_t)i * rk + k];
-      if (X) {
+  for (int i0 = tl.row0; i0 < tl.row1; i0 += RB) {
+    const int nr = min(RB, tl.row1 - i0);
+    __syncthreads();  // the previous block's reads of s_x are done
+    for (int e = threadIdx.x; e < nr * RC; e += BLOCK) s_x[e] = X ? (double)X[(size_t)i0 * RC + e] : v[i0 + e];
+    __syncthreads();
+    // wave w takes rows w, w + 4, ... of the tile, in order (RB is a
+    // multiple of the wave count)
+    if (k < rk)
+      for (int r = wave; r < nr; r += BLOCK / 64) {
+        const double kv = (double)K[(size_t)(i0 + r) * rk + k];
 #pragma unroll
-        for (int c = 0; c < RC; ++c) acc[c] += kv * (double)X[(size_t)i * RC + c];
-      } else {
-        acc[0] += kv * v[i];
+        for (int c = 0; c < RC; ++c) acc[c] += kv * s_x[r * RC + c];
       }
-    }
+  }
   for (int c = 0; c < RC; ++c) {
     s_red[wave][lane] = acc[c];
     __syncthreads();
@@ -2490,8 +2498,9 @@ __global__ __launch_bounds__(BLOCK) void k_lc_sum(const int32_t *__restrict__ il
 // (Algorithm 5), for the rows of each tile: a wave per row, its lanes over
 // the columns k of K (coalesced reads of the row of K), a wave reduction per
 // output column.  vec 0: R columns from the Z-slot zsel into lc_W[zsel]
-// (rows of stride R), K in the operator type; vec 1: the Lanczos vector's
-// coefficients lc_zv into lc_wv, K in FP64.
+// (rows of stride R), K in the operator type -- launched for R = 2 only, the
+// tiled form below takes R >= 4; vec 1: the Lanczos vector's coefficients
+// lc_zv into lc_wv, K in FP64.
 template <typename T, int R>
 __global__ __launch_bounds__(BLOCK) void k_lc_kz(const Tile *__restrict__ tiles, const InstDev *__restrict__ insts,
                                                  int32_t zsel, int32_t vec) {
@@ -2530,11 +2539,12 @@ __global__ __launch_bounds__(BLOCK) void k_lc_kz(const Tile *__restrict__ tiles,
   }
 }
 
-// Wide factors (R >= 16): the same two contractions tiled through LDS, so
-// that a row of X or of Z is read once per block of rows rather than once
-// per row.  K^T X per tile: the block's rows of X staged in LDS, lane =
-// column k of K, wave = a group of R/4 output columns, each (k, c) summed
-// over the tile's rows in row order; into lc_part[tile][k][c] as above.
+// The same two contractions tiled through LDS, so that a row of X or of Z
+// is read once per block of rows rather than once per row.  K^T X for wide
+// factors (R >= 16) per tile: the block's rows of X staged in LDS, lane =
+// column k of K, wave = a group of R/4 output columns (no cross-wave sums),
+// each (k, c) summed over the tile's rows in row order; into
+// lc_part[tile][k][c] as above.
 template <typename T, int R>
 __global__ __launch_bounds__(BLOCK) void k_lc_kty_wide(const Tile *__restrict__ tiles,
                                                        const InstDev *__restrict__ insts, int32_t xrole) {
@@ -2575,14 +2585,16 @@ __global__ __launch_bounds__(BLOCK) void k_lc_kty_wide(const Tile *__restrict__ 
   }
 }
 
-// K Z for wide factors: per block of 64 rows of the tile, the columns of K
-// in chunks of 32 -- the chunk of K (transposed, padded) and the matching 32
-// rows of Z staged in LDS -- lane = row, wave = a group of R/4 output
-// columns, each output summed over k in order; into lc_W[zsel].
+// K Z for R >= 4 columns: per block of 64 rows of the tile, the columns of
+// K in chunks of 32 -- the chunk of K (transposed, padded) and the matching
+// 32 rows of Z staged in LDS -- lane = row, wave = a group of R/4 output
+// columns, each output summed over k in order; into lc_W[zsel].  (A wave per
+// row re-read all of Z, rk x R, from the L2 for every row of K: 244 KB per
+// row at R = 8.)
 template <typename T, int R>
-__global__ __launch_bounds__(BLOCK) void k_lc_kz_wide(const Tile *__restrict__ tiles,
+__global__ __launch_bounds__(BLOCK) void k_lc_kz_tiled(const Tile *__restrict__ tiles,
                                                       const InstDev *__restrict__ insts, int32_t zsel) {
-  static_assert(R >= 16 && R % (BLOCK / 64) == 0, "wide factors only");
+  static_assert(R >= 4 && R % (BLOCK / 64) == 0, "four or more columns");
   constexpr int CW = R / (BLOCK / 64);
   constexpr int RB = 64, KC = 32;
   __shared__ double sK[KC * (RB + 1)];
@@ -2677,10 +2689,10 @@ void op_lc_kz(int prec, int R, hipStream_t s, const Tile *t, int nt, const InstD
     break;
 #define HL_KZW(RR)                                                                                            \
   case RR:                                                                                                  \
-    if (is64(prec)) hipLaunchKernelGGL((k_lc_kz_wide<double, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel); \
-    else hipLaunchKernelGGL((k_lc_kz_wide<float, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel);            \
+    if (is64(prec)) hipLaunchKernelGGL((k_lc_kz_tiled<double, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel); \
+    else hipLaunchKernelGGL((k_lc_kz_tiled<float, RR>), dim3(nt), dim3(BLOCK), 0, s, t, d, zsel);            \
     break;
-    HL_KZ(2) HL_KZ(4) HL_KZ(8) HL_KZW(16) HL_KZW(32) HL_KZW(64)
+    HL_KZ(2) HL_KZW(4) HL_KZW(8) HL_KZW(16) HL_KZW(32) HL_KZW(64)
 #undef HL_KZ
 #undef HL_KZW
     default: break;
