@@ -2434,17 +2434,30 @@ __global__ __launch_bounds__(RBLOCK) void k_lc_red(const int32_t *__restrict__ i
     for (int q = threadIdx.x; q < I.nlc; q += blockDim.x)
       if (I.lc_off[q + 1] - I.lc_off[q] <= 8) out[q] = lc_quad(I, q, Y, ld, R, 0, 1);
     __shared__ double red[RBLOCK / 64];
-    for (int q = 0; q < I.nlc; ++q) {
-      if (I.lc_off[q + 1] - I.lc_off[q] <= 8) continue;
-      double v = wave_sum(lc_quad(I, q, Y, ld, R, threadIdx.x, blockDim.x));
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __shared__ int s_any;
+    // the terms checked a block at a time (one flag per block of terms), so
+    // that only blocks holding a larger term are walked term by term
+    for (int q0 = 0; q0 < I.nlc; q0 += blockDim.x) {
+      if (threadIdx.x == 0) s_any = 0;
       __syncthreads();
-      if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-        out[q] = s;
+      const int qt = q0 + threadIdx.x;
+      if (qt < I.nlc && I.lc_off[qt + 1] - I.lc_off[qt] > 8) s_any = 1;
+      __syncthreads();
+      const bool any = s_any != 0;
+      __syncthreads();  // every thread has read the flag before it is reset
+      if (!any) continue;
+      for (int q = q0; q < min(I.nlc, q0 + (int)blockDim.x); ++q) {
+        if (I.lc_off[q + 1] - I.lc_off[q] <= 8) continue;
+        double v = wave_sum(lc_quad(I, q, Y, ld, R, threadIdx.x, blockDim.x));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double s = 0.0;
+          for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+          out[q] = s;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     return;
   }
